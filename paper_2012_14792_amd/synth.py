@@ -1,0 +1,138 @@
+"""Seeded synthetic inputs: 10-bit luma frames and per-CTU encoding-time maps.
+
+The paper measures on JVET common-test-condition sequences (FHD and UHD, Section 3.1),
+which are not available here.  These generators produce frames of the same resolutions,
+bit depth and CTU grid, with spatially varying texture, and CTU times that are temporally
+correlated (the property the co-located-CTU estimator of Section 2.1 relies on).
+
+This module is the only code shared by the oracle-side tests and the GPU path.  It holds
+none of the partitioning method's arithmetic: no features, no cost map, no search.  The
+time model takes a per-CTU texture array as an *input*; callers supply it.
+
+Frame recipe (fixed draw order from ``numpy.random.Generator(PCG64(seed))``):
+  1. 8 sinusoids: period P ~ logU[4, 256] px, angle ~ U[0, pi), phase ~ U[0, 2 pi),
+     amplitude ~ U[20, 80].  Drawn as four arrays of length 8 in that order.
+  2. 20 blobs: centre x ~ U[0, w), centre y ~ U[0, h), sigma ~ U[8, 200],
+     amplitude ~ U[50, 300], speed ~ U[0, drift_max], heading ~ U[0, 2 pi).
+     Drawn as six arrays of length 20 in that order.
+  3. For each blob in order: a noise patch u ~ U[-1, 1] of shape (2R+1, 2R+1), R = ceil(3 sigma).
+  Luma = clip(rint(512 + sum of sinusoids + sum of blob patches), 0, 1023) as uint16.
+  A blob contributes a * exp(-r^2 / (2 sigma^2)) * u inside its (2R+1)^2 window and nothing
+  outside it; at frame f its window is centred at round(centre + f * velocity), so the noise
+  moves with the blob.  Sinusoids do not move.
+
+Time recipe: T_f(c) = round((200 + 3 tex_f(c)) * exp(eps_f(c))) microseconds, with
+eps_0 ~ N(0, 0.3^2) and eps_f = rho eps_{f-1} + sqrt(1 - rho^2) N(0, 0.3^2).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "FrameSpec", "SequenceGenerator", "make_frame", "ar1_eps", "ctu_times",
+    "CONFIGS", "ctu_grid",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class FrameSpec:
+    width: int
+    height: int
+    ctu: int = 128
+    bit_depth: int = 10
+
+
+def ctu_grid(width: int, height: int, ctu: int = 128) -> tuple[int, int]:
+    """Number of CTU columns and rows covering the frame (partial CTUs count)."""
+    return (width + ctu - 1) // ctu, (height + ctu - 1) // ctu
+
+
+class SequenceGenerator:
+    """A drifting-blob sequence; ``frame(f)`` renders frame f (f >= 0)."""
+
+    def __init__(self, width: int, height: int, seed: int, drift_max: float = 0.0,
+                 n_sin: int = 8, n_blobs: int = 20, base: float = 512.0):
+        self.width, self.height = int(width), int(height)
+        rng = np.random.Generator(np.random.PCG64(seed))
+        period = np.exp(rng.uniform(math.log(4.0), math.log(256.0), n_sin))
+        angle = rng.uniform(0.0, math.pi, n_sin)
+        phase = rng.uniform(0.0, 2.0 * math.pi, n_sin)
+        amp = rng.uniform(20.0, 80.0, n_sin)
+        bx = rng.uniform(0.0, width, n_blobs)
+        by = rng.uniform(0.0, height, n_blobs)
+        bsig = rng.uniform(8.0, 200.0, n_blobs)
+        bamp = rng.uniform(50.0, 300.0, n_blobs)
+        bspeed = rng.uniform(0.0, drift_max, n_blobs) if drift_max > 0 else np.zeros(n_blobs)
+        bhead = rng.uniform(0.0, 2.0 * math.pi, n_blobs)
+        self.blobs = []
+        for i in range(n_blobs):
+            rad = int(math.ceil(3.0 * bsig[i]))
+            noise = rng.uniform(-1.0, 1.0, (2 * rad + 1, 2 * rad + 1))
+            yy, xx = np.mgrid[-rad:rad + 1, -rad:rad + 1]
+            env = np.exp(-(xx * xx + yy * yy) / (2.0 * bsig[i] ** 2))
+            patch = (bamp[i] * env * noise).astype(np.float32)
+            vx = bspeed[i] * math.cos(bhead[i])
+            vy = bspeed[i] * math.sin(bhead[i])
+            self.blobs.append((bx[i], by[i], vx, vy, rad, patch))
+        # Static sinusoid field, float32, computed once per sequence.
+        ys = np.arange(height, dtype=np.float64)[:, None]
+        xs = np.arange(width, dtype=np.float64)[None, :]
+        fld = np.full((height, width), base, dtype=np.float64)
+        for k in range(n_sin):
+            arg = (xs * math.cos(angle[k]) + ys * math.sin(angle[k])) * (2.0 * math.pi / period[k])
+            fld += amp[k] * np.sin(arg + phase[k])
+        self.base = fld.astype(np.float32)
+
+    def frame(self, f: int = 0) -> np.ndarray:
+        h, w = self.height, self.width
+        img = self.base.copy()
+        for (bx, by, vx, vy, rad, patch) in self.blobs:
+            cx = int(round(bx + f * vx))
+            cy = int(round(by + f * vy))
+            x0, y0 = cx - rad, cy - rad
+            x1, y1 = cx + rad + 1, cy + rad + 1
+            sx0, sy0 = max(x0, 0), max(y0, 0)
+            sx1, sy1 = min(x1, w), min(y1, h)
+            if sx0 >= sx1 or sy0 >= sy1:
+                continue
+            img[sy0:sy1, sx0:sx1] += patch[sy0 - y0:sy1 - y0, sx0 - x0:sx1 - x0]
+        np.rint(img, out=img)
+        np.clip(img, 0.0, 1023.0, out=img)
+        return img.astype(np.uint16)
+
+
+def make_frame(width: int, height: int, seed: int) -> np.ndarray:
+    """A single still frame (frame 0 of a non-drifting sequence)."""
+    return SequenceGenerator(width, height, seed).frame(0)
+
+
+def ar1_eps(n_ctu: int, n_frames: int, seed: int, rho: float = 0.8,
+            sigma: float = 0.3) -> np.ndarray:
+    """AR(1) log-noise per CTU, shape (n_frames, n_ctu); marginal N(0, sigma^2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eps = np.empty((n_frames, n_ctu), dtype=np.float64)
+    eps[0] = rng.normal(0.0, sigma, n_ctu)
+    s = math.sqrt(1.0 - rho * rho)
+    for f in range(1, n_frames):
+        eps[f] = rho * eps[f - 1] + s * rng.normal(0.0, sigma, n_ctu)
+    return eps
+
+
+def ctu_times(tex: np.ndarray, eps: np.ndarray, a: float = 200.0, b: float = 3.0) -> np.ndarray:
+    """Synthetic measured CTU times in microseconds: round((a + b tex) e^eps), uint32."""
+    t = np.rint((a + b * np.asarray(tex, dtype=np.float64)) * np.exp(eps))
+    return np.clip(t, 1, 2**31 - 1).astype(np.uint32)
+
+
+# Workload configurations (sizes, thread budgets and search bounds).
+CONFIGS = {
+    "fhd_n4": dict(width=1920, height=1080, frames=1, n_threads=4, max_tile_cols=3,
+                   max_tile_rows=3, max_rs_per_tile=2, lam=(0, 1), seed=1, drift=0.0),
+    "uhd_n8": dict(width=3840, height=2160, frames=64, n_threads=8, max_tile_cols=6,
+                   max_tile_rows=4, max_rs_per_tile=4, lam=(1, 10), seed=2, drift=8.0),
+    "8k_n16": dict(width=7680, height=4320, frames=32, n_threads=16, max_tile_cols=8,
+                   max_tile_rows=6, max_rs_per_tile=4, lam=(1, 10), seed=3, drift=8.0),
+}
