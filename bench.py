@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of the TRS partitioning path on one MI355X.
+
+Workload: the 4K sequence -- 64 frames of 3840x2160 10-bit luma (30 x 17 CTUs of 128),
+N = 8 slices/threads, tile grids up to 6 x 4, up to 4 slices per tile, lambda = 1/10, the
+ladder rule's (3, 1) window: 5,914,718 candidates per frame.  One step = every frame of
+the sequence through features -> predicted time map -> two-step exhaustive search, one frame
+per launch sequence, inputs (luma and previous-frame CTU times) resident in HBM.
+
+Prints one JSON line: frames/s (4K frames partitioned per second) with candidates scored
+per second, the dominant kernel's roofline fraction (HIP events around it, on its stream),
+and the CPU oracle timed on a bounded sample of the same workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12      # 32-bit VALU lane-ops: CUs x lanes/clk x clock
+METRIC = "4K frames partitioned/s + TRS candidates scored/s (1 GPU, bit-exact vs oracle)"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0: 2 x cores)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=16, help="oracle worker threads (cap)")
+    ap.add_argument("--sched-block", type=int, default=0)
+    ap.add_argument("--sched-item", type=int, default=0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build partitions frames on a single MI355X "
+              "and has no multi-GPU path (frames would shard across GPUs with no communication).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2012_14792_amd import binding as B
+    from paper_2012_14792_amd import synth
+
+    cfg = synth.CONFIGS["uhd_n8"]
+    w, h, F = cfg["width"], cfg["height"], args.frames
+    torch.cuda.set_device(0)
+    params = B.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
+                           cfg["max_rs_per_tile"], lam=cfg["lam"], sched_block=args.sched_block,
+                           sched_item=args.sched_item)
+    frame = B.make_frame(w, h)
+    stats = B.trs_search_stats(frame, params)
+    W, H = B.ctu_dims(frame)
+
+    # ---- inputs: seeded synthetic sequence, rendered on the host, resident in HBM ----------
+    t0 = time.perf_counter()
+    gen = synth.SequenceGenerator(w, h, cfg["seed"], cfg["drift"])
+    with cf.ThreadPoolExecutor(8) as ex:
+        frames = list(ex.map(gen.frame, range(F)))
+    luma = torch.empty((F, h, w), dtype=torch.int16, device="cuda")
+    for f in range(F):
+        luma[f].copy_(torch.from_numpy(frames[f].view(np.int16)))
+    # measured CTU times: the synthetic time model on each frame's texture (GPU features)
+    texs = []
+    for f in range(F):
+        feats = B.alloc_features(frame)
+        B.trs_features(frame, luma[f], feats)
+        texs.append(feats["tex"].cpu().numpy().view(np.uint32))
+    eps = synth.ar1_eps(W * H, F, cfg["seed"] + 1000)
+    truth = [synth.ctu_times(texs[f], eps[f]) for f in range(F)]
+    prev_np = [truth[max(f - 1, 0)] for f in range(F)]
+    prev = torch.stack([torch.from_numpy(p.view(np.int32)) for p in prev_np]).cuda()
+    torch.cuda.synchronize()
+    log(f"inputs ready: {F} frames {w}x{h} in {time.perf_counter() - t0:.1f} s; "
+        f"{stats['candidates']} candidates/frame, {stats['items']} work items")
+
+    part = B.Partitioner(w, h, params)
+    outs = torch.empty((F, B.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+
+    def step():
+        for f in range(F):
+            part.enqueue(luma[f], prev[f], out=outs[f])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    B.trs_profile_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    B.trs_profile_enable(False)
+    ms1, ms2, n_search = B.trs_profile_read()
+    elapsed = t_end - t_start
+    fps = F * args.steps / elapsed
+    log(f"timed {args.steps} steps in {elapsed:.3f} s: {fps:.1f} frames/s")
+
+    # ---- roofline of the dominant kernel (step 1 or step 2 of the search) -----------------
+    avg1, avg2 = ms1 / max(n_search, 1), ms2 / max(n_search, 1)
+    # algorithmic 32-bit lane-ops of step 1 per launch: per candidate 5 per tile record
+    # (64-bit max, 32-bit min, 32-bit max) + 8 (area test, minimum, count); per record slice
+    # 12 (rectangle sum, area, extrema)
+    ops1 = 5 * stats["tile_lookups"] + 8 * stats["candidates"] + 12 * stats["record_slices"]
+    dominant = "k_search<256, false> (step 1)" if avg1 >= avg2 else "k_search<256, true> (step 2)"
+    achieved = ops1 / (avg1 * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
+                "unit": "Tops/s", "frac": round(achieved / PEAK_ALU_TOPS, 4), "traffic": None,
+                "kernel": "k_search<256, false> (step 1)", "avg_ms": round(avg1, 5),
+                "ops_per_launch": ops1, "dominant": dominant,
+                "step2_avg_ms": round(avg2, 5)}
+
+    # ---- CPU oracle on a bounded sample, on the host's cores ------------------------------
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = min(len(os.sched_getaffinity(0)), args.cpu_threads)
+        S = min(F, args.cpu_frames or 2 * cores)
+        oparams = oracle.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
+                                     cfg["max_rs_per_tile"], lam=cfg["lam"])
+        otex = [oracle.features(frames[f])["tex"] for f in range(S)]
+        oprev = [synth.ctu_times(otex[max(f - 1, 0)], eps[max(f - 1, 0)]) for f in range(S)]
+        log(f"cpu baseline: oracle on {S} frames with {cores} threads")
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(cores) as ex:
+            refs = list(ex.map(lambda f: oracle.partition(frames[f], oprev[f], oparams), range(S)))
+        wall = time.perf_counter() - t0
+        cpu = {"value": round(S / wall, 4), "unit": "4K frames/s", "cores": cores, "kind": "oracle",
+               "sample": f"frames 0..{S - 1} of the same 64-frame 4K sequence, whole path "
+                         f"(features, time map, two-step search), one frame per thread, "
+                         f"{wall:.1f} s wall"}
+        host = B.Result
+        ok = 0
+        for f in range(S):
+            g = B.result_dict(host.from_buffer_copy(bytes(outs[f].cpu().numpy().tobytes())))
+            r = refs[f]
+            same = all(g[k] == r[k] for k in ("rank", "t_min", "t_sel", "q_sel", "n_feasible", "rs_time")) \
+                and [tuple(x) for x in g["rs"]] == [tuple(x) for x in r["rs"]]
+            ok += same
+        parity = f"{ok}/{S} frames bit-exact vs oracle"
+        log(parity)
+
+    res = {
+        "metric": METRIC,
+        "value": round(fps, 3),
+        "unit": "4K frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"4K sequence: {F} frames 3840x2160 10-bit, CTU 128 (30x17), "
+                               f"N=8 slices, tiles <= 6x4, <= 4 slices/tile, lambda=1/10, "
+                               f"window ({stats['dtile']},{stats['drs']}), "
+                               f"{stats['candidates']} candidates/frame, one frame per launch",
+                   "frames": F, "width": w, "height": h, "n_threads": 8,
+                   "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
+                   "sched_block": args.sched_block or 256, "sched_item": args.sched_item or 4096},
+        "candidates_scored_per_s": round(fps * stats["candidates"], 1),
+        "kernel_ms": {"step1": round(avg1, 5), "step2": round(avg2, 5)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

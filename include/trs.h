@@ -1,0 +1,202 @@
+/*
+ * trs.h -- C ABI of the MI355X (gfx950) dynamic tile + rectangular-slice (TRS) frame
+ * partitioning library (libtrs.so).
+ *
+ * Method: Amestoy, Hamidouche, Bergeron, Menard, "Quality-driven Dynamic VVC Frame
+ * Partitioning for efficient Parallel Processing", ICIP 2020.  Before a frame is encoded
+ * by N threads, one rectangular slice (RS) per thread, the frame is cut into a tile grid and
+ * each tile into runs of whole CTU rows (Section 1).  Step 1 finds the smallest predicted
+ * parallel time T~min (Eq. 1, Eq. 3) from per-CTU time predictions; step 2 picks, among
+ * partitions with T~(P) <= T~min (1 + lambda) (Eq. 4), the one with the least within-RS luma
+ * squared error (Eq. 2).  Only partitions with k A_min(P) > A_max(P) are searched
+ * (Section 2.3, k = 3).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named *_dev (and every array argument of the launch calls) are device
+ *     pointers owned by the caller; the library never frees them.  Host pointers are marked.
+ *   - Launch calls are asynchronous on the given HIP stream: they validate their scalar
+ *     arguments on the host, enqueue kernels and return.  A negative status means nothing
+ *     was enqueued and no output was written.  Data-dependent outcomes (no feasible
+ *     partition, cost overflow) are reported in device memory (trs_result.status, the cost
+ *     flag word) once the stream reaches them.
+ *   - Per-CTU arrays are in raster order (row of CTUs after row), W = ceil(width / ctu),
+ *     H = ceil(height / ctu); right and bottom CTUs may be partial.
+ *   - The first search on a given (frame geometry, search parameters) pair builds the
+ *     candidate-space tables on the host and uploads them to the current device
+ *     (synchronous, allocated once and kept until trs_release_plans() or process exit).
+ *     Later calls with the same pair only enqueue kernels.
+ *   - Thread safety: calls may come from several host threads; plan construction is
+ *     serialised internally.  Two searches that share one workspace must be ordered by the
+ *     caller (same stream or events).
+ */
+#ifndef TRS_H
+#define TRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum trs_status {
+    TRS_OK = 0,
+    TRS_ENOFEASIBLE = 1,   /* warning: no area-feasible partition; the uniform one is returned */
+    TRS_EINVAL = -1,       /* invalid argument */
+    TRS_ERANGE = -2,       /* overflow guard tripped */
+    TRS_ENOSPACE = -3,     /* candidate space empty, above 2^40, or beyond table limits */
+    TRS_EWORKSPACE = -4,   /* workspace missing or smaller than trs_search_workspace() */
+    TRS_EDEVICE = -5,      /* a HIP runtime call failed */
+    TRS_ENOTIMPL = -6
+} trs_status;
+
+/* Frame geometry.  width, height in [1, 8192]; ctu_size in {32, 64, 128} (VVC uses 128);
+ * bit_depth in [8, 12].  Sample values above 2^bit_depth - 1 are the caller's contract. */
+typedef struct trs_frame {
+    int32_t width, height, ctu_size, bit_depth;
+} trs_frame;
+
+/* Per-CTU features, device arrays of W*H entries (Section 2.2 needs the RS luma sums S1, S2
+ * that Eq. 2 expands to; tex/mean/var describe the texture for time models).
+ *   s1   = sum of samples, s2 = sum of squared samples, grad = G, the sum over samples
+ *          (x, y) of the CTU of |p(x+1,y) - p(x,y)| + |p(x,y+1) - p(x,y)|, each term taken
+ *          only when the neighbour lies inside the frame (it may lie in the next CTU);
+ *   tex  = floor(G / n), mean = floor(s1 / n), var = floor((n s2 - s1^2) / n^2),
+ *          with n the CTU's sample count. */
+typedef struct trs_feat {
+    uint32_t *s1, *grad, *tex, *mean, *var;
+    uint64_t *s2;
+} trs_feat;
+
+/* Time-map blend (Section 2.1: the predicted time of a CTU is the measured time of the
+ * co-located CTU in the previous frame of the same temporal layer, w_prev = 256).
+ * cost = floor((w_prev prev + (256 - w_prev) (a + b tex) + 128) / 256) when prev is given,
+ * a + b tex otherwise.  w_prev in [0, 256]. */
+typedef struct trs_blend {
+    uint32_t a, b, w_prev;
+} trs_blend;
+
+/* Search parameters.
+ *   n_threads       N, the number of RS (= encoding threads), 1..64;
+ *   max_tile_cols/rows, max_rs_per_tile: bounds Cmax, Rmax, Kmax of the candidate space;
+ *   area_k          k of the balance rule k A_min > A_max (Section 2.3); 0 disables it;
+ *   lambda_num/den  lambda = num / den of Eq. 4, 0 <= num <= 65535, 1 <= den <= 65535;
+ *                   num < 0 means lambda = infinity (pure Eq. 2 clustering);
+ *   dtile, drs      window (in CTUs) of tile boundaries around the uniform positions and of
+ *                   RS split offsets inside a tile; -1 = unbounded; both -2 = ladder rule:
+ *                   the first of (inf,inf), (3,1), (2,1), (1,1), (1,0), (0,0) whose space
+ *                   holds at most space_budget candidates (else (0,0));
+ *   space_budget    ladder budget, <= 0 means 2^24;
+ *   sched_block     work-group size for the search kernels (64, 128, 256, 512; 0 = 256);
+ *   sched_item      target candidates per work item (0 = library default).  The schedule
+ *                   changes speed only, never the result. */
+typedef struct trs_search_params {
+    int32_t n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile;
+    int32_t area_k, lambda_num, lambda_den;
+    int32_t dtile, drs;
+    int32_t sched_block, sched_item;
+    int64_t space_budget;
+} trs_search_params;
+
+#define TRS_MAX_RS 64
+
+/* Result of one search (written to device memory by trs_search).
+ *   rank          canonical rank of the chosen partition (order: tile-grid shape (c, r)
+ *                 ascending, column boundaries X, row boundaries Y lexicographic, then the
+ *                 per-tile (k, split offsets) choices with the first tile in raster order
+ *                 most significant); -1 if the fallback uniform grid is outside the space;
+ *   t_min         T~min of Eq. 3 (-1 when nothing is feasible);
+ *   t_sel, q_sel  T~(P) (Eq. 1) and Q(P) = sum over RS of S2 - floor(S1^2 / n) (Eq. 2 in
+ *                 exact integers) of the chosen partition; ties in Q are broken by smaller
+ *                 T~(P), then by smaller rank;
+ *   n_enumerated  |C|; n_feasible: candidates passing the area rule;
+ *   uniform_rank, t_unif, q_unif: rank and scores of the uniform c_u x r_u grid
+ *                 (c_u r_u = N, most square, c_u >= r_u, one RS per tile);
+ *   status        TRS_OK or TRS_ENOFEASIBLE;
+ *   col_bd/row_bd tile boundaries in CTUs (tile_cols + 1 and tile_rows + 1 entries);
+ *   rs[i]         RS rectangles {x0, y0, x1, y1} in CTUs (half open), tiles in raster
+ *                 order, top to bottom inside a tile; rs_time[i] its predicted time. */
+typedef struct trs_result {
+    int64_t rank, t_min, t_sel, q_sel, n_enumerated, n_feasible, uniform_rank, t_unif, q_unif;
+    int32_t status, tile_cols, tile_rows, n_rs, dtile_used, drs_used;
+    int32_t col_bd[TRS_MAX_RS + 1], row_bd[TRS_MAX_RS + 1];
+    int32_t rs[TRS_MAX_RS][4];
+    int64_t rs_time[TRS_MAX_RS];
+} trs_result;
+
+/* Per-CTU luma features (inputs of Eq. 2; Section 2.2).  luma: device, uint16 samples,
+ * row r at luma + r * stride_elems; stride_elems >= width, a multiple of 8, and luma
+ * 16-byte aligned.  out: device arrays of W*H entries each (all six required).
+ * Errors: TRS_EINVAL (geometry, alignment, null), TRS_EDEVICE (launch failure). */
+trs_status trs_features(const trs_frame *frame, const uint16_t *luma, int64_t stride_elems,
+                        trs_feat out, hipStream_t stream);
+
+/* Predicted per-CTU time map T~(c) (Section 2.1).  tex, prev, cost: device, W*H entries;
+ * prev may be NULL (first frame: texture model only).  flags_dev: NULL or a device uint32
+ * that the kernel ORs with 1 when a value exceeds 2^31 - 1 (the value is then clamped).
+ * Errors: TRS_EINVAL, TRS_EDEVICE. */
+trs_status trs_cost_map(const trs_frame *frame, const uint32_t *tex, const uint32_t *prev,
+                        trs_blend blend, uint32_t *cost, uint32_t *flags_dev,
+                        hipStream_t stream);
+
+/* Host: workspace bytes trs_search needs for this geometry and parameters (builds the
+ * candidate-space plan if it does not exist yet).  Errors: TRS_EINVAL, TRS_ENOSPACE. */
+trs_status trs_search_workspace(const trs_frame *frame, const trs_search_params *params,
+                                size_t *bytes);
+
+/* The two-step search (Eq. 3, then Eq. 2 under Eq. 4, area rule of Section 2.3) over the
+ * candidate space, exhaustive and exact.  cost: T~ per CTU (u32); s1, s2: per-CTU luma sums
+ * from trs_features; workspace: device, at least trs_search_workspace() bytes, 256-byte
+ * aligned, contents need not be initialised; out_dev: device trs_result.
+ * Errors: TRS_EINVAL, TRS_ENOSPACE, TRS_EWORKSPACE, TRS_EDEVICE. */
+trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
+                      const uint32_t *cost, const uint32_t *s1, const uint64_t *s2,
+                      void *workspace, size_t ws_bytes, trs_result *out_dev,
+                      hipStream_t stream);
+
+/* Host: |C| and the windows (dtile, drs) the ladder rule picks.  No device work.
+ * Errors: TRS_EINVAL. */
+trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params,
+                          int64_t *n, int32_t *dtile, int32_t *drs);
+
+/* Work done by one trs_search for this geometry and these parameters (host only; builds
+ * the plan if needed).  candidates = |C|; tile_lookups = sum over candidates of their tile
+ * count (each step combines one tile-option record per tile); items = work items (one
+ * work-group each); records / record_slices = tile-option records built per step and the
+ * slices they sum; table_bytes = size of the device tables.  Errors: as trs_search_workspace. */
+typedef struct trs_plan_stats {
+    int64_t candidates, tile_lookups, items, records, record_slices, table_bytes;
+    int32_t dtile, drs;
+} trs_plan_stats;
+
+trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *params,
+                            trs_plan_stats *out);
+
+/* Host: decode a canonical rank into the tile grid and RS rectangles (out_host fields
+ * rank, tile_cols, tile_rows, col_bd, row_bd, n_rs, rs, dtile_used, drs_used,
+ * n_enumerated; times and scores are left 0).  Errors: TRS_EINVAL (rank out of range),
+ * TRS_ENOSPACE. */
+trs_status trs_decode(const trs_frame *frame, const trs_search_params *params, int64_t rank,
+                      trs_result *out_host);
+
+/* Kernel timing.  While enabled (on != 0), every trs_search records HIP events on its
+ * stream before step 1, between step 1 and step 2, and after step 2.  trs_profile_read
+ * waits for the recorded events, returns the summed milliseconds of the step-1 and step-2
+ * kernels and the number of searches timed, and clears the record.  Host only; returns
+ * TRS_EDEVICE if an event call fails. */
+void trs_profile_enable(int on);
+trs_status trs_profile_read(double *ms_step1, double *ms_step2, int64_t *searches);
+
+/* Host: drop every cached candidate-space plan and free its device tables. */
+void trs_release_plans(void);
+
+/* Static description of a status code. */
+const char *trs_strerror(trs_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRS_H */

@@ -1,0 +1,290 @@
+"""ctypes binding of libtrs.so.
+
+Argument marshalling only: every step of the partitioning path runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream.  The module raises
+at import of the library if libtrs.so is missing (build it with
+``python -m paper_2012_14792_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrs.so")
+
+TRS_OK, TRS_ENOFEASIBLE = 0, 1
+TRS_EINVAL, TRS_ERANGE, TRS_ENOSPACE, TRS_EWORKSPACE, TRS_EDEVICE, TRS_ENOTIMPL = -1, -2, -3, -4, -5, -6
+MAX_RS = 64
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("ctu_size", ctypes.c_int32), ("bit_depth", ctypes.c_int32)]
+
+
+class Feat(ctypes.Structure):
+    _fields_ = [("s1", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("tex", ctypes.c_void_p),
+                ("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("s2", ctypes.c_void_p)]
+
+
+class Blend(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_uint32), ("b", ctypes.c_uint32), ("w_prev", ctypes.c_uint32)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("n_threads", ctypes.c_int32), ("max_tile_cols", ctypes.c_int32),
+                ("max_tile_rows", ctypes.c_int32), ("max_rs_per_tile", ctypes.c_int32),
+                ("area_k", ctypes.c_int32), ("lambda_num", ctypes.c_int32),
+                ("lambda_den", ctypes.c_int32), ("dtile", ctypes.c_int32), ("drs", ctypes.c_int32),
+                ("sched_block", ctypes.c_int32), ("sched_item", ctypes.c_int32),
+                ("space_budget", ctypes.c_int64)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int64), ("tile_lookups", ctypes.c_int64),
+                ("items", ctypes.c_int64), ("records", ctypes.c_int64),
+                ("record_slices", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
+                ("dtile", ctypes.c_int32), ("drs", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("t_min", ctypes.c_int64), ("t_sel", ctypes.c_int64),
+                ("q_sel", ctypes.c_int64), ("n_enumerated", ctypes.c_int64),
+                ("n_feasible", ctypes.c_int64), ("uniform_rank", ctypes.c_int64),
+                ("t_unif", ctypes.c_int64), ("q_unif", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("n_rs", ctypes.c_int32),
+                ("dtile_used", ctypes.c_int32), ("drs_used", ctypes.c_int32),
+                ("col_bd", ctypes.c_int32 * (MAX_RS + 1)), ("row_bd", ctypes.c_int32 * (MAX_RS + 1)),
+                ("rs", (ctypes.c_int32 * 4) * MAX_RS), ("rs_time", ctypes.c_int64 * MAX_RS)]
+
+
+RESULT_BYTES = ctypes.sizeof(Result)
+_lib = None
+
+
+class TrsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+def lib():
+    """Load libtrs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2012_14792_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, S = ctypes.c_void_p, ctypes.c_int
+        L.trs_features.argtypes = [ctypes.POINTER(Frame), P, ctypes.c_int64, Feat, P]
+        L.trs_features.restype = S
+        L.trs_cost_map.argtypes = [ctypes.POINTER(Frame), P, P, Blend, P, P, P]
+        L.trs_cost_map.restype = S
+        L.trs_search_workspace.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+        L.trs_search_workspace.restype = S
+        L.trs_search.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams), P, P, P, P,
+                                 ctypes.c_size_t, P, P]
+        L.trs_search.restype = S
+        L.trs_space_size.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
+        L.trs_space_size.restype = S
+        L.trs_search_stats.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams),
+                                       ctypes.POINTER(PlanStats)]
+        L.trs_search_stats.restype = S
+        L.trs_decode.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams),
+                                 ctypes.c_int64, ctypes.POINTER(Result)]
+        L.trs_decode.restype = S
+        L.trs_release_plans.argtypes = []
+        L.trs_release_plans.restype = None
+        L.trs_profile_enable.argtypes = [S]
+        L.trs_profile_enable.restype = None
+        L.trs_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
+        L.trs_profile_read.restype = S
+        L.trs_strerror.argtypes = [S]
+        L.trs_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().trs_strerror(int(status)).decode()
+
+
+def check(status: int, where: str) -> int:
+    if status < 0:
+        raise TrsError(status, where)
+    if status > 0:
+        warnings.warn(f"{where}: {strerror(status)}", RuntimeWarning, stacklevel=3)
+    return status
+
+
+def make_frame(width: int, height: int, ctu_size: int = 128, bit_depth: int = 10) -> Frame:
+    return Frame(width, height, ctu_size, bit_depth)
+
+
+def make_params(n_threads: int, max_tile_cols: int, max_tile_rows: int, max_rs_per_tile: int,
+                area_k: int = 3, lam=(0, 1), dtile: int = -2, drs: int = -2,
+                sched_block: int = 0, sched_item: int = 0, space_budget: int = 1 << 24) -> SearchParams:
+    num, den = lam
+    return SearchParams(n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile, area_k,
+                        num, den, dtile, drs, sched_block, sched_item, space_budget)
+
+
+# ---- host-only calls ---------------------------------------------------------------------
+
+def trs_space_size(frame: Frame, params: SearchParams) -> tuple[int, int, int]:
+    n, dt, dr = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().trs_space_size(ctypes.byref(frame), ctypes.byref(params), ctypes.byref(n),
+                               ctypes.byref(dt), ctypes.byref(dr)), "trs_space_size")
+    return n.value, dt.value, dr.value
+
+
+def trs_search_workspace(frame: Frame, params: SearchParams) -> int:
+    b = ctypes.c_size_t()
+    check(lib().trs_search_workspace(ctypes.byref(frame), ctypes.byref(params), ctypes.byref(b)),
+          "trs_search_workspace")
+    return b.value
+
+
+def trs_search_stats(frame: Frame, params: SearchParams) -> dict:
+    st = PlanStats()
+    check(lib().trs_search_stats(ctypes.byref(frame), ctypes.byref(params), ctypes.byref(st)),
+          "trs_search_stats")
+    return {k: getattr(st, k) for k, _ in PlanStats._fields_}
+
+
+def trs_decode(frame: Frame, params: SearchParams, rank: int) -> dict:
+    r = Result()
+    check(lib().trs_decode(ctypes.byref(frame), ctypes.byref(params), int(rank), ctypes.byref(r)),
+          "trs_decode")
+    return result_dict(r)
+
+
+def trs_profile_enable(on: bool) -> None:
+    lib().trs_profile_enable(1 if on else 0)
+
+
+def trs_profile_read() -> tuple[float, float, int]:
+    a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    check(lib().trs_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)), "trs_profile_read")
+    return a.value, b.value, n.value
+
+
+def trs_release_plans() -> None:
+    lib().trs_release_plans()
+
+
+def result_dict(r: Result) -> dict:
+    n = r.n_rs
+    return dict(
+        status=r.status, rank=r.rank, t_min=r.t_min, t_sel=r.t_sel, q_sel=r.q_sel,
+        n_enumerated=r.n_enumerated, n_feasible=r.n_feasible, uniform_rank=r.uniform_rank,
+        t_unif=r.t_unif, q_unif=r.q_unif, tile_cols=r.tile_cols, tile_rows=r.tile_rows,
+        n_rs=n, dtile_used=r.dtile_used, drs_used=r.drs_used,
+        col_bd=[r.col_bd[i] for i in range(r.tile_cols + 1)] if r.tile_cols else [],
+        row_bd=[r.row_bd[j] for j in range(r.tile_rows + 1)] if r.tile_rows else [],
+        rs=[tuple(r.rs[q][e] for e in range(4)) for q in range(n)],
+        rs_time=[r.rs_time[q] for q in range(n)],
+    )
+
+
+# ---- device calls on torch tensors ---------------------------------------------------------
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ctu_dims(frame: Frame) -> tuple[int, int]:
+    cs = frame.ctu_size
+    return (frame.width + cs - 1) // cs, (frame.height + cs - 1) // cs
+
+
+def alloc_features(frame: Frame, device="cuda"):
+    import torch
+    W, H = ctu_dims(frame)
+    n = W * H
+    return {k: torch.empty(n, dtype=torch.int32, device=device) for k in ("s1", "grad", "tex", "mean", "var")} | \
+        {"s2": torch.empty(n, dtype=torch.int64, device=device)}
+
+
+def trs_features(frame: Frame, luma, feats: dict, stream=None) -> dict:
+    """luma: 2-D uint16 (or int16) CUDA tensor [height, >= width], row stride a multiple of 8."""
+    if luma.dim() != 2 or luma.element_size() != 2 or not luma.is_cuda:
+        raise TrsError(TRS_EINVAL, "trs_features")
+    if luma.stride(1) != 1:
+        raise TrsError(TRS_EINVAL, "trs_features")
+    f = Feat(feats["s1"].data_ptr(), feats["grad"].data_ptr(), feats["tex"].data_ptr(),
+             feats["mean"].data_ptr(), feats["var"].data_ptr(), feats["s2"].data_ptr())
+    check(lib().trs_features(ctypes.byref(frame), _ptr(luma), luma.stride(0), f, _stream(stream)),
+          "trs_features")
+    return feats
+
+
+def trs_cost_map(frame: Frame, tex, prev, blend: Blend, cost, flags=None, stream=None):
+    check(lib().trs_cost_map(ctypes.byref(frame), _ptr(tex), None if prev is None else _ptr(prev),
+                             blend, _ptr(cost), None if flags is None else _ptr(flags),
+                             _stream(stream)), "trs_cost_map")
+    return cost
+
+
+def trs_search(frame: Frame, params: SearchParams, cost, s1, s2, workspace, out, stream=None):
+    """Enqueue the search; `out` is a CUDA uint8 tensor of RESULT_BYTES bytes."""
+    check(lib().trs_search(ctypes.byref(frame), ctypes.byref(params), _ptr(cost), _ptr(s1), _ptr(s2),
+                           _ptr(workspace), workspace.numel() * workspace.element_size(),
+                           _ptr(out), _stream(stream)), "trs_search")
+    return out
+
+
+def read_result(out) -> dict:
+    """Copy a device trs_result to the host (synchronises on it) and decode it."""
+    raw = bytes(out.cpu().numpy().tobytes())
+    r = Result.from_buffer_copy(raw)
+    d = result_dict(r)
+    if d["status"] == TRS_ENOFEASIBLE:
+        warnings.warn("trs_search: no area-feasible partition; uniform partition returned",
+                      RuntimeWarning, stacklevel=2)
+    return d
+
+
+class Partitioner:
+    """Whole per-frame path on one device: features -> cost map -> two-step search.
+
+    Holds device buffers for one frame geometry and parameter set.
+    """
+
+    def __init__(self, width, height, params: SearchParams, ctu_size=128, bit_depth=10,
+                 blend=(200, 3, 256), device="cuda"):
+        import torch
+        self.frame = make_frame(width, height, ctu_size, bit_depth)
+        self.params = params
+        self.blend = Blend(*blend)
+        self.W, self.H = ctu_dims(self.frame)
+        self.feats = alloc_features(self.frame, device)
+        self.cost = torch.empty(self.W * self.H, dtype=torch.int32, device=device)
+        self.flags = torch.zeros(1, dtype=torch.int32, device=device)
+        ws = trs_search_workspace(self.frame, params)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=device)
+        self.out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=device)
+
+    def enqueue(self, luma, prev, out=None, stream=None):
+        trs_features(self.frame, luma, self.feats, stream)
+        trs_cost_map(self.frame, self.feats["tex"], prev, self.blend, self.cost, self.flags, stream)
+        trs_search(self.frame, self.params, self.cost, self.feats["s1"], self.feats["s2"], self.ws,
+                   self.out if out is None else out, stream)
+        return self.out if out is None else out
+
+    def __call__(self, luma, prev, stream=None) -> dict:
+        self.enqueue(luma, prev, stream=stream)
+        return read_result(self.out)

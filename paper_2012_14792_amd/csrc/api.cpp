@@ -1,0 +1,332 @@
+// C ABI of libtrs.so (declarations and contracts in include/trs.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <array>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "space.hpp"
+#include "trs.h"
+
+namespace {
+
+using trs::Plan;
+
+struct PlanEntry {
+    std::unique_ptr<Plan> plan;
+    std::map<int, std::pair<void *, trs::SpaceView>> dev;   // per device: blob and view
+};
+
+std::mutex g_mu;
+std::map<std::vector<int64_t>, PlanEntry> g_plans;
+
+// Timing events recorded by trs_search while profiling is on (guarded by g_prof_mu).
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::array<hipEvent_t, 3>> g_prof_events;
+
+std::vector<int64_t> plan_key(const trs_frame *f, const trs_search_params *p)
+{
+    return {f->width, f->height, f->ctu_size, p->n_threads, p->max_tile_cols, p->max_tile_rows,
+            p->max_rs_per_tile, p->dtile, p->drs,
+            p->space_budget > 0 ? p->space_budget : (int64_t(1) << 24), p->sched_item};
+}
+
+// Host tables for (f, p), built once.  Caller holds g_mu.
+trs_status host_plan(const trs_frame *f, const trs_search_params *p, PlanEntry **out)
+{
+    auto key = plan_key(f, p);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) {
+        auto pl = std::make_unique<Plan>();
+        trs_status st = trs::build_plan(f, p, *pl);
+        if (st != TRS_OK) return st;
+        it = g_plans.emplace(key, PlanEntry{std::move(pl), {}}).first;
+    }
+    *out = &it->second;
+    return TRS_OK;
+}
+
+template <typename T>
+size_t add_array(std::vector<std::tuple<const void *, size_t, size_t>> &parts, size_t &off,
+                 const std::vector<T> &v)
+{
+    off = (off + 255) & ~size_t(255);
+    size_t at = off;
+    size_t bytes = v.size() * sizeof(T);
+    parts.emplace_back(v.data(), bytes, at);
+    off += bytes ? bytes : 1;
+    return at;
+}
+
+// Device copy of the plan on the current device.  Caller holds g_mu.
+trs_status device_view(PlanEntry &e, trs::SpaceView *view)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TRS_EDEVICE;
+    auto it = e.dev.find(dev);
+    if (it != e.dev.end()) {
+        *view = it->second.second;
+        return TRS_OK;
+    }
+    const Plan &pl = *e.plan;
+    std::vector<std::tuple<const void *, size_t, size_t>> parts;
+    size_t off = 0;
+    size_t o_colpx = add_array(parts, off, pl.colpx);
+    size_t o_rowpx = add_array(parts, off, pl.rowpx);
+    size_t o_obase = add_array(parts, off, pl.opt_base);
+    size_t o_okcnt = add_array(parts, off, pl.opt_kcnt);
+    size_t o_ok = add_array(parts, off, pl.opt_k);
+    size_t o_oz = add_array(parts, off, pl.opt_z);
+    size_t o_shapes = add_array(parts, off, pl.shapes);
+    size_t o_xtab = add_array(parts, off, pl.xtab);
+    size_t o_ytab = add_array(parts, off, pl.ytab);
+    size_t o_prefM = add_array(parts, off, pl.y_prefM);
+    size_t o_ycombo = add_array(parts, off, pl.y_combo);
+    size_t o_yM = add_array(parts, off, pl.y_M);
+    size_t o_combos = add_array(parts, off, pl.combos);
+    size_t o_items = add_array(parts, off, pl.items);
+    size_t o_spans = add_array(parts, off, pl.spans);
+    size_t o_map = add_array(parts, off, pl.spanmap);
+    size_t o_unif = add_array(parts, off, pl.unif_rs);
+    const size_t bytes = (off + 255) & ~size_t(255);
+    std::vector<char> host(bytes, 0);
+    for (auto &pt : parts)
+        if (std::get<1>(pt)) std::memcpy(host.data() + std::get<2>(pt), std::get<0>(pt), std::get<1>(pt));
+    void *blob = nullptr;
+    if (hipMalloc(&blob, bytes) != hipSuccess) return TRS_EDEVICE;
+    if (hipMemcpy(blob, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(blob);
+        return TRS_EDEVICE;
+    }
+    char *b = static_cast<char *>(blob);
+    trs::SpaceView v{};
+    v.colpx = reinterpret_cast<const int32_t *>(b + o_colpx);
+    v.rowpx = reinterpret_cast<const int32_t *>(b + o_rowpx);
+    v.opt_base = reinterpret_cast<const int32_t *>(b + o_obase);
+    v.opt_kcnt = reinterpret_cast<const int32_t *>(b + o_okcnt);
+    v.opt_k = reinterpret_cast<const uint8_t *>(b + o_ok);
+    v.opt_z = reinterpret_cast<const uint16_t *>(b + o_oz);
+    v.shapes = reinterpret_cast<const trs::ShapeDev *>(b + o_shapes);
+    v.xtab = reinterpret_cast<const uint16_t *>(b + o_xtab);
+    v.ytab = reinterpret_cast<const uint16_t *>(b + o_ytab);
+    v.y_prefM = reinterpret_cast<const int64_t *>(b + o_prefM);
+    v.y_combo = reinterpret_cast<const int64_t *>(b + o_ycombo);
+    v.y_M = reinterpret_cast<const int32_t *>(b + o_yM);
+    v.combos = reinterpret_cast<const uint16_t *>(b + o_combos);
+    v.items = reinterpret_cast<const trs::ItemDev *>(b + o_items);
+    v.spans = reinterpret_cast<const uint16_t *>(b + o_spans);
+    v.spanmap = reinterpret_cast<const uint8_t *>(b + o_map);
+    v.unif_rs = reinterpret_cast<const int32_t *>(b + o_unif);
+    v.W = pl.W;
+    v.H = pl.H;
+    v.N = pl.N;
+    v.Km = pl.Km;
+    v.n_items = (int32_t)pl.items.size();
+    v.n_shapes = (int32_t)pl.shapes.size();
+    v.n_unif = pl.n_unif;
+    v.total = pl.total;
+    v.uniform_rank = pl.uniform_rank;
+    e.dev[dev] = {blob, v};
+    *view = v;
+    return TRS_OK;
+}
+
+bool frame_ok(const trs_frame *f)
+{
+    return f && f->width >= 1 && f->height >= 1 && f->width <= 8192 && f->height <= 8192 &&
+           (f->ctu_size == 32 || f->ctu_size == 64 || f->ctu_size == 128) &&
+           f->bit_depth >= 8 && f->bit_depth <= 12;
+}
+
+}  // namespace
+
+extern "C" {
+
+trs_status trs_features(const trs_frame *frame, const uint16_t *luma, int64_t stride_elems,
+                        trs_feat out, hipStream_t stream)
+{
+    if (!frame_ok(frame) || !luma) return TRS_EINVAL;
+    if (stride_elems < frame->width || stride_elems % 8 != 0) return TRS_EINVAL;
+    if (reinterpret_cast<uintptr_t>(luma) % 16 != 0) return TRS_EINVAL;
+    if (!out.s1 || !out.s2 || !out.grad || !out.tex || !out.mean || !out.var) return TRS_EINVAL;
+    hipError_t e = trs::launch_features(frame->width, frame->height, frame->ctu_size, luma,
+                                        stride_elems, out, stream);
+    return e == hipSuccess ? TRS_OK : TRS_EDEVICE;
+}
+
+trs_status trs_cost_map(const trs_frame *frame, const uint32_t *tex, const uint32_t *prev,
+                        trs_blend blend, uint32_t *cost, uint32_t *flags_dev, hipStream_t stream)
+{
+    if (!frame_ok(frame) || !tex || !cost || blend.w_prev > 256) return TRS_EINVAL;
+    const int cs = frame->ctu_size;
+    const int n = ((frame->width + cs - 1) / cs) * ((frame->height + cs - 1) / cs);
+    hipError_t e = trs::launch_cost_map(n, tex, prev, blend, cost, flags_dev, stream);
+    return e == hipSuccess ? TRS_OK : TRS_EDEVICE;
+}
+
+trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params, int64_t *n,
+                          int32_t *dtile, int32_t *drs)
+{
+    if (!n || !dtile || !drs) return TRS_EINVAL;
+    trs_status st = trs::check_space_args(frame, params);
+    if (st != TRS_OK) return st;
+    const int cs = frame->ctu_size;
+    return trs::space_size((frame->width + cs - 1) / cs, (frame->height + cs - 1) / cs, params,
+                           n, dtile, drs);
+}
+
+trs_status trs_search_workspace(const trs_frame *frame, const trs_search_params *params,
+                                size_t *bytes)
+{
+    if (!bytes) return TRS_EINVAL;
+    trs_status st = trs::check_space_args(frame, params);
+    if (st != TRS_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    PlanEntry *e = nullptr;
+    st = host_plan(frame, params, &e);
+    if (st != TRS_OK) return st;
+    *bytes = trs::ws_layout(*e->plan).total;
+    return TRS_OK;
+}
+
+trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
+                      const uint32_t *cost, const uint32_t *s1, const uint64_t *s2,
+                      void *workspace, size_t ws_bytes, trs_result *out_dev, hipStream_t stream)
+{
+    trs_status st = trs::check_space_args(frame, params);
+    if (st != TRS_OK) return st;
+    if (!cost || !s1 || !s2 || !out_dev) return TRS_EINVAL;
+    trs::SearchArgs a{};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        PlanEntry *e = nullptr;
+        st = host_plan(frame, params, &e);
+        if (st != TRS_OK) return st;
+        a.lay = trs::ws_layout(*e->plan);
+        if (!workspace || ws_bytes < a.lay.total || reinterpret_cast<uintptr_t>(workspace) % 256)
+            return TRS_EWORKSPACE;
+        st = device_view(*e, &a.sp);
+        if (st != TRS_OK) return st;
+        a.dt = e->plan->dt;
+        a.dr = e->plan->dr;
+    }
+    a.cost = cost;
+    a.s1 = s1;
+    a.s2 = s2;
+    a.ws = static_cast<char *>(workspace);
+    a.out = out_dev;
+    a.area_k = params->area_k;
+    a.lam_num = params->lambda_num < 0 ? -1 : params->lambda_num;
+    a.lam_den = params->lambda_den;
+    a.block = params->sched_block ? params->sched_block : 256;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (g_prof_on) {
+            std::array<hipEvent_t, 3> ev{};
+            for (auto &x : ev)
+                if (hipEventCreate(&x) != hipSuccess) return TRS_EDEVICE;
+            g_prof_events.push_back(ev);
+            for (int i = 0; i < 3; i++) a.ev[i] = ev[i];
+        }
+    }
+    return trs::launch_search(a, stream) == hipSuccess ? TRS_OK : TRS_EDEVICE;
+}
+
+void trs_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+}
+
+trs_status trs_profile_read(double *ms_step1, double *ms_step2, int64_t *searches)
+{
+    if (!ms_step1 || !ms_step2 || !searches) return TRS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double a = 0, b = 0;
+    trs_status st = TRS_OK;
+    for (auto &ev : g_prof_events) {
+        float x = 0, y = 0;
+        if (hipEventSynchronize(ev[2]) != hipSuccess || hipEventElapsedTime(&x, ev[0], ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&y, ev[1], ev[2]) != hipSuccess)
+            st = TRS_EDEVICE;
+        a += x;
+        b += y;
+    }
+    *ms_step1 = a;
+    *ms_step2 = b;
+    *searches = (int64_t)g_prof_events.size();
+    for (auto &ev : g_prof_events)
+        for (auto &x : ev) (void)hipEventDestroy(x);
+    g_prof_events.clear();
+    return st;
+}
+
+trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *params,
+                            trs_plan_stats *out)
+{
+    if (!out) return TRS_EINVAL;
+    trs_status st = trs::check_space_args(frame, params);
+    if (st != TRS_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    PlanEntry *e = nullptr;
+    st = host_plan(frame, params, &e);
+    if (st != TRS_OK) return st;
+    const Plan &pl = *e->plan;
+    out->candidates = pl.total;
+    out->tile_lookups = pl.tile_lookups;
+    out->items = (int64_t)pl.items.size();
+    out->records = pl.records;
+    out->record_slices = pl.record_slices;
+    out->table_bytes = (int64_t)(pl.combos.size() * 2 + pl.xtab.size() * 2 + pl.ytab.size() * 2 +
+                                 pl.items.size() * sizeof(trs::ItemDev) + pl.spans.size() * 2 +
+                                 pl.spanmap.size() + pl.opt_z.size() * 2);
+    out->dtile = pl.dt;
+    out->drs = pl.dr;
+    return TRS_OK;
+}
+
+trs_status trs_decode(const trs_frame *frame, const trs_search_params *params, int64_t rank,
+                      trs_result *out_host)
+{
+    if (!out_host) return TRS_EINVAL;
+    trs_status st = trs::check_space_args(frame, params);
+    if (st != TRS_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    PlanEntry *e = nullptr;
+    st = host_plan(frame, params, &e);
+    if (st != TRS_OK) return st;
+    std::memset(out_host, 0, sizeof(*out_host));
+    return trs::decode_rank(*e->plan, rank, out_host);
+}
+
+void trs_release_plans(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_plans)
+        for (auto &d : kv.second.dev) (void)hipFree(d.second.first);
+    g_plans.clear();
+}
+
+const char *trs_strerror(trs_status s)
+{
+    switch (s) {
+    case TRS_OK: return "ok";
+    case TRS_ENOFEASIBLE: return "no area-feasible partition; uniform partition returned";
+    case TRS_EINVAL: return "invalid argument";
+    case TRS_ERANGE: return "value out of range";
+    case TRS_ENOSPACE: return "candidate space empty or beyond table limits";
+    case TRS_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case TRS_EDEVICE: return "HIP runtime error";
+    case TRS_ENOTIMPL: return "not implemented";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+// Internal launch interface between the C ABI layer and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "space.hpp"
+
+namespace trs {
+
+// Search workspace header (device), followed by the SATs and per-item arrays.
+struct WsHeader {
+    unsigned long long tmin;        // step 1 minimum over feasible candidates
+    unsigned long long nfeas;       // feasible candidates counted in step 1
+    unsigned long long pruned;      // step-2 work items skipped by their step-1 minimum
+    unsigned long long pad[5];
+};
+
+// One work item's step-2 winner (q = UINT64_MAX when it has none).
+struct Partial {
+    unsigned long long q, t;
+    long long rank;
+    int32_t item, f;
+};
+
+struct WsLayout {
+    size_t header, satT, satS1, satS2, item_min, partial, total;
+};
+
+WsLayout ws_layout(const Plan &pl);
+
+struct SearchArgs {
+    SpaceView sp;
+    const uint32_t *cost, *s1;
+    const uint64_t *s2;
+    char *ws;
+    WsLayout lay;
+    trs_result *out;
+    int area_k;
+    int lam_num, lam_den;             // lam_num < 0: infinite
+    int block;                        // work-group size of the search kernels
+    int dt, dr;
+    hipEvent_t ev[3];                 // optional timing events (all null when not profiling)
+};
+
+hipError_t launch_features(int w, int h, int cs, const uint16_t *luma, int64_t stride,
+                           const trs_feat &out, hipStream_t s);
+hipError_t launch_cost_map(int n, const uint32_t *tex, const uint32_t *prev, trs_blend b,
+                           uint32_t *cost, uint32_t *flags, hipStream_t s);
+hipError_t launch_search(const SearchArgs &a, hipStream_t s);
+
+}  // namespace trs

@@ -1,0 +1,532 @@
+// Host construction of the candidate-space plan (see space.hpp).
+#include "space.hpp"
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <utility>
+
+namespace trs {
+namespace {
+
+using u64 = uint64_t;
+
+u64 sadd(u64 a, u64 b) { u64 s = a + b; return s < a ? UINT64_MAX : s; }
+u64 smul(u64 a, u64 b)
+{
+    if (!a || !b) return 0;
+    unsigned __int128 p = (unsigned __int128)a * b;
+    return p > (unsigned __int128)UINT64_MAX ? UINT64_MAX : (u64)p;
+}
+
+// Boundary b may be the i-th of m - 1 interior boundaries of [0, L] under window d.
+inline bool legal(int b, int i, int m, int L, int d)
+{
+    if (d < 0) return true;
+    int centre = (int)(((int64_t)i * L) / m);
+    return std::abs(b - centre) <= d;
+}
+
+// Number of legal strictly increasing (b_1 .. b_{m-1}) in [1, L - 1].
+u64 count_vectors(int m, int L, int d)
+{
+    if (m < 1 || m > L) return 0;
+    if (m == 1) return 1;
+    std::vector<u64> cur(L + 1, 0), nxt(L + 1, 0);
+    for (int b = 1; b < L; b++) cur[b] = legal(b, 1, m, L, d) ? 1 : 0;
+    for (int i = 2; i < m; i++) {
+        u64 below = 0;                       // sum of cur[b'] over b' < b
+        for (int b = 0; b < L; b++) {
+            nxt[b] = (b >= 1 && legal(b, i, m, L, d)) ? below : 0;
+            below = sadd(below, cur[b]);
+        }
+        std::swap(cur, nxt);
+    }
+    u64 total = 0;
+    for (int b = 1; b < L; b++) total = sadd(total, cur[b]);
+    return total;
+}
+
+// Lexicographic list of the vectors above, each stored as m + 1 values 0, b_1 .. b_{m-1}, L.
+bool list_vectors(int m, int L, int d, int64_t cap, std::vector<uint16_t> &out, int64_t &n)
+{
+    n = 0;
+    if (m < 1 || m > L) return true;
+    std::vector<int> cur(m + 1, 0);
+    cur[0] = 0;
+    cur[m] = L;
+    // iterative depth-first walk: position i in [1, m-1]
+    if (m == 1) {
+        out.push_back(0);
+        out.push_back((uint16_t)L);
+        n = 1;
+        return true;
+    }
+    int i = 1;
+    cur[1] = 0;
+    while (i >= 1) {
+        int b = cur[i] + 1;
+        // remaining boundaries after i need room: b <= L - 1 - (m - 1 - i)
+        int hi = L - 1 - (m - 1 - i);
+        while (b <= hi && !legal(b, i, m, L, d)) b++;
+        if (b > hi) {                         // exhausted this level: backtrack
+            i--;
+            continue;
+        }
+        cur[i] = b;
+        if (i == m - 1) {
+            if (n >= cap) return false;
+            for (int q = 0; q <= m; q++) out.push_back((uint16_t)cur[q]);
+            n++;
+        } else {
+            i++;
+            cur[i] = cur[i - 1];
+        }
+    }
+    return true;
+}
+
+// P_h(z) truncated at degree N: coefficient k = number of split vectors of a height-h tile
+// into k slices (k <= Kmax).
+void tile_poly(int h, int N, int Km, int dr, std::vector<u64> &P)
+{
+    P.assign(N + 1, 0);
+    for (int k = 1; k <= std::min(std::min(Km, h), N); k++) P[k] = count_vectors(k, h, dr);
+}
+
+void poly_mul(const std::vector<u64> &a, const std::vector<u64> &b, std::vector<u64> &out, int N)
+{
+    out.assign(N + 1, 0);
+    for (int i = 0; i <= N; i++) {
+        if (!a[i]) continue;
+        for (int j = 0; i + j <= N; j++)
+            if (b[j]) out[i + j] = sadd(out[i + j], smul(a[i], b[j]));
+    }
+}
+
+// |C| for one window pair, by a DP over tile-row boundaries (no enumeration of Y).
+u64 space_count(int W, int H, const trs_search_params *p, int dt, int dr)
+{
+    const int N = p->n_threads, Km = p->max_rs_per_tile;
+    std::vector<std::vector<u64>> P(H + 1);
+    for (int h = 1; h <= H; h++) tile_poly(h, N, Km, dr, P[h]);
+    u64 total = 0;
+    for (int c = 1; c <= p->max_tile_cols; c++) {
+        u64 nx = count_vectors(c, W, dt);
+        if (!nx) continue;
+        // P_h^c for every h
+        std::vector<std::vector<u64>> Pc(H + 1);
+        for (int h = 1; h <= H; h++) {
+            std::vector<u64> acc(N + 1, 0), tmp;
+            acc[0] = 1;
+            for (int rep = 0; rep < c; rep++) { poly_mul(acc, P[h], tmp, N); acc.swap(tmp); }
+            Pc[h] = acc;
+        }
+        for (int r = 1; r <= p->max_tile_rows; r++) {
+            if (!((int64_t)c * r <= N && (int64_t)N <= (int64_t)Km * c * r)) continue;
+            if (r > H) continue;
+            // F[y] = polynomial over ways to place the first j row boundaries ending at y
+            std::vector<std::vector<u64>> F(H + 1, std::vector<u64>(N + 1, 0)), G;
+            F[0][0] = 1;
+            for (int j = 1; j <= r; j++) {
+                G.assign(H + 1, std::vector<u64>(N + 1, 0));
+                for (int y = 1; y <= H; y++) {
+                    if (j < r && (y == H || !legal(y, j, r, H, dt))) continue;
+                    if (j == r && y != H) continue;
+                    for (int yp = 0; yp < y; yp++) {
+                        bool any = false;
+                        for (int q = 0; q <= N && !any; q++) any = F[yp][q] != 0;
+                        if (!any) continue;
+                        std::vector<u64> prod;
+                        poly_mul(F[yp], Pc[y - yp], prod, N);
+                        for (int q = 0; q <= N; q++) G[y][q] = sadd(G[y][q], prod[q]);
+                    }
+                }
+                F.swap(G);
+            }
+            total = sadd(total, smul(nx, F[H][N]));
+        }
+    }
+    return total;
+}
+
+const int kLadder[6][2] = {{-1, -1}, {3, 1}, {2, 1}, {1, 1}, {1, 0}, {0, 0}};
+
+}  // namespace
+
+trs_status check_space_args(const trs_frame *f, const trs_search_params *p)
+{
+    if (!f || !p) return TRS_EINVAL;
+    if (f->width < 1 || f->height < 1 || f->width > 8192 || f->height > 8192) return TRS_EINVAL;
+    if (f->ctu_size != 32 && f->ctu_size != 64 && f->ctu_size != 128) return TRS_EINVAL;
+    if (f->bit_depth < 8 || f->bit_depth > 12) return TRS_EINVAL;
+    if (p->n_threads < 1 || p->n_threads > kMaxRS) return TRS_EINVAL;
+    if (p->max_tile_cols < 1 || p->max_tile_rows < 1 || p->max_rs_per_tile < 1) return TRS_EINVAL;
+    if (p->max_tile_cols > kMaxRS || p->max_tile_rows > kMaxRS) return TRS_EINVAL;
+    if (p->area_k < 0 || p->area_k > 1000000) return TRS_EINVAL;
+    if (p->lambda_den < 1 || p->lambda_den > 65535 || p->lambda_num > 65535) return TRS_EINVAL;
+    bool ladder = p->dtile == -2 && p->drs == -2;
+    if (!ladder && (p->dtile < -1 || p->drs < -1)) return TRS_EINVAL;
+    if (p->sched_block != 0 && p->sched_block != 64 && p->sched_block != 128 &&
+        p->sched_block != 256 && p->sched_block != 512) return TRS_EINVAL;
+    if (p->sched_item < 0) return TRS_EINVAL;
+    return TRS_OK;
+}
+
+trs_status space_size(int W, int H, const trs_search_params *p, int64_t *n, int32_t *dt, int32_t *dr)
+{
+    if (W < 1 || H < 1 || W > kMaxGrid || H > kMaxGrid) return TRS_EINVAL;
+    int a, b;
+    if (p->dtile == -2 && p->drs == -2) {
+        u64 budget = p->space_budget > 0 ? (u64)p->space_budget : (u64(1) << 24);
+        int pick = 5;
+        for (int i = 0; i < 6; i++)
+            if (space_count(W, H, p, kLadder[i][0], kLadder[i][1]) <= budget) { pick = i; break; }
+        a = kLadder[pick][0];
+        b = kLadder[pick][1];
+    } else {
+        a = p->dtile;
+        b = p->drs;
+    }
+    u64 s = space_count(W, H, p, a, b);
+    *n = s > (u64)INT64_MAX ? INT64_MAX : (int64_t)s;
+    *dt = a;
+    *dr = b;
+    return TRS_OK;
+}
+
+trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
+{
+    trs_status st = check_space_args(f, p);
+    if (st != TRS_OK) return st;
+    const int cs = f->ctu_size;
+    const int W = (f->width + cs - 1) / cs, H = (f->height + cs - 1) / cs;
+    const int N = p->n_threads, Km = p->max_rs_per_tile;
+    pl.width = f->width;
+    pl.height = f->height;
+    pl.cs = cs;
+    pl.N = N;
+    pl.Cm = p->max_tile_cols;
+    pl.Rm = p->max_tile_rows;
+    pl.Km = Km;
+    pl.dtile_req = p->dtile;
+    pl.drs_req = p->drs;
+    pl.item_target = p->sched_item;
+    pl.budget = p->space_budget;
+    pl.W = W;
+    pl.H = H;
+    st = space_size(W, H, p, &pl.total, &pl.dt, &pl.dr);
+    if (st != TRS_OK) return st;
+    if (pl.total <= 0 || pl.total > kSpaceCap) return TRS_ENOSPACE;
+    const int dt = pl.dt, dr = pl.dr;
+
+    pl.colpx.assign(W + 1, 0);
+    pl.rowpx.assign(H + 1, 0);
+    for (int x = 0; x < W; x++) pl.colpx[x + 1] = pl.colpx[x] + std::min(cs, f->width - x * cs);
+    for (int y = 0; y < H; y++) pl.rowpx[y + 1] = pl.rowpx[y] + std::min(cs, f->height - y * cs);
+
+    // Shapes with their X and Y lists.
+    struct ShapeHost { int c, r; std::vector<uint16_t> X, Y; int64_t nX, nY; };
+    std::vector<ShapeHost> sh;
+    std::vector<char> height_used(H + 1, 0);
+    const int64_t vec_cap = int64_t(1) << 24;
+    for (int c = 1; c <= p->max_tile_cols; c++) {
+        for (int r = 1; r <= p->max_tile_rows; r++) {
+            if (!((int64_t)c * r <= N && (int64_t)N <= (int64_t)Km * c * r)) continue;
+            ShapeHost s{c, r, {}, {}, 0, 0};
+            if (!list_vectors(c, W, dt, vec_cap, s.X, s.nX)) return TRS_ENOSPACE;
+            if (!list_vectors(r, H, dt, vec_cap, s.Y, s.nY)) return TRS_ENOSPACE;
+            if (!s.nX || !s.nY) continue;
+            for (int64_t yi = 0; yi < s.nY; yi++)
+                for (int j = 0; j < r; j++)
+                    height_used[s.Y[yi * (r + 1) + j + 1] - s.Y[yi * (r + 1) + j]] = 1;
+            sh.push_back(std::move(s));
+        }
+    }
+
+    // Options per used height: k ascending, Z lexicographic; opt_z rows of Km + 1 entries.
+    pl.opt_base.assign(H + 2, 0);
+    pl.opt_kcnt.assign((size_t)(H + 1) * (Km + 1), 0);
+    for (int h = 1; h <= H; h++) {
+        pl.opt_base[h] = (int32_t)pl.opt_k.size();
+        int cnt = 0;
+        if (height_used[h]) {
+            for (int k = 1; k <= std::min(std::min(Km, h), N); k++) {
+                std::vector<uint16_t> zs;
+                int64_t nz = 0;
+                if (!list_vectors(k, h, dr, 65536, zs, nz)) return TRS_ENOSPACE;
+                for (int64_t q = 0; q < nz; q++) {
+                    pl.opt_k.push_back((uint8_t)k);
+                    for (int e = 0; e <= Km; e++)
+                        pl.opt_z.push_back(e <= k ? zs[q * (k + 1) + e] : (uint16_t)h);
+                }
+                cnt += (int)nz;
+                if (cnt > 65535) return TRS_ENOSPACE;
+                pl.opt_kcnt[(size_t)h * (Km + 1) + k] = cnt;
+            }
+        }
+        for (int k = 1; k <= Km; k++) {
+            size_t i = (size_t)h * (Km + 1) + k;
+            if (pl.opt_kcnt[i] < pl.opt_kcnt[i - 1]) pl.opt_kcnt[i] = pl.opt_kcnt[i - 1];
+        }
+    }
+    pl.opt_base[H + 1] = (int32_t)pl.opt_k.size();
+    auto kcnt = [&](int h, int kk) { return pl.opt_kcnt[(size_t)h * (Km + 1) + std::min(kk, Km)]; };
+
+    // Combination tables per (shape, Y), in canonical order.
+    int64_t rank_base = 0;
+    const int64_t target = p->sched_item > 0 ? p->sched_item : 4096;
+    for (auto &s : sh) {
+        const int c = s.c, r = s.r, T = c * r;
+        const int kcap = std::min(Km, N - (T - 1));
+        ShapeDev sd{};
+        sd.c = c; sd.r = r; sd.T = T; sd.kcap = kcap;
+        sd.nX = s.nX; sd.nY = s.nY;
+        sd.x_off = (int64_t)pl.xtab.size();
+        sd.y_off = (int64_t)pl.ytab.size();
+        sd.yinfo_off = (int64_t)pl.y_M.size();
+        int64_t SM = 0;
+        std::vector<int> heights(T);
+        for (int64_t yi = 0; yi < s.nY; yi++) {
+            const uint16_t *Y = &s.Y[yi * (r + 1)];
+            for (int t = 0; t < T; t++) heights[t] = Y[t / c + 1] - Y[t / c];
+            // comp[t][n]: ways for tiles t..T-1 to hold n slices (saturating)
+            std::vector<u64> comp((size_t)(T + 1) * (N + 1), 0);
+            comp[(size_t)T * (N + 1) + 0] = 1;
+            for (int t = T - 1; t >= 0; t--) {
+                int h = heights[t];
+                for (int n = 0; n <= N; n++) {
+                    u64 acc = 0;
+                    for (int k = 1; k <= std::min(kcap, std::min(h, n)); k++) {
+                        u64 ways = (u64)(kcnt(h, k) - kcnt(h, k - 1));
+                        acc = sadd(acc, smul(ways, comp[(size_t)(t + 1) * (N + 1) + n - k]));
+                    }
+                    comp[(size_t)t * (N + 1) + n] = acc;
+                }
+            }
+            u64 M = comp[N];
+            if (M > (u64)INT32_MAX) return TRS_ENOSPACE;
+            pl.y_prefM.push_back(SM);
+            pl.y_M.push_back((int32_t)M);
+            pl.y_combo.push_back((int64_t)pl.combos.size());
+            if ((int64_t)pl.combos.size() + (int64_t)M * T > kComboCap) return TRS_ENOSPACE;
+            if (M) {
+                size_t off = pl.combos.size();
+                pl.combos.resize(off + (size_t)M * T);
+                // depth-first walk in canonical order; cur[t] = local option index
+                std::vector<int> cur(T, 0), kk(T, 0), left(T + 1, 0);
+                int64_t m = 0;
+                // explicit stack: for each tile, iterate over options with usable k
+                std::vector<int> opt_end(T, 0);
+                int t = 0;
+                left[0] = N;
+                bool descend = true;
+                while (t >= 0) {
+                    int h = (t < T) ? heights[t] : 0;
+                    if (t == T) {
+                        for (int q = 0; q < T; q++) pl.combos[off + (size_t)q * M + m] = (uint16_t)cur[q];
+                        m++;
+                        t--;
+                        descend = false;
+                        continue;
+                    }
+                    int o;
+                    if (descend) {
+                        o = 0;
+                    } else {
+                        o = cur[t] + 1;
+                    }
+                    // advance o to the next option whose k leaves a completable remainder
+                    int n = left[t];
+                    int last = kcnt(h, std::min(kcap, n));
+                    while (o < last) {
+                        int k = pl.opt_k[pl.opt_base[h] + o];
+                        if (comp[(size_t)(t + 1) * (N + 1) + n - k]) break;
+                        o = kcnt(h, k);                      // skip every option with this k
+                    }
+                    if (o >= last) {
+                        t--;
+                        descend = false;
+                        continue;
+                    }
+                    cur[t] = o;
+                    left[t + 1] = n - pl.opt_k[pl.opt_base[h] + o];
+                    t++;
+                    descend = true;
+                }
+                if (m != (int64_t)M) return TRS_EINVAL;      // internal consistency
+            }
+            SM += (int64_t)M;
+        }
+        if (SM == 0) {
+            pl.y_prefM.resize(sd.yinfo_off);
+            pl.y_M.resize(sd.yinfo_off);
+            pl.y_combo.resize(sd.yinfo_off);
+            continue;
+        }
+        sd.SM = SM;
+        sd.rank_base = rank_base;
+        pl.xtab.insert(pl.xtab.end(), s.X.begin(), s.X.end());
+        pl.ytab.insert(pl.ytab.end(), s.Y.begin(), s.Y.end());
+        const int32_t shape_idx = (int32_t)pl.shapes.size();
+
+        // Work items: consecutive X vectors of one Y, sized by the candidate target and by
+        // the LDS record / span-map capacities.
+        for (int64_t yi = 0; yi < s.nY; yi++) {
+            const int32_t M = pl.y_M[sd.yinfo_off + yi];
+            if (!M) continue;
+            const uint16_t *Y = &s.Y[yi * (r + 1)];
+            int rrow = 0, rslices = 0;
+            for (int j = 0; j < r; j++) {
+                int h = Y[j + 1] - Y[j];
+                int n_opt = kcnt(h, std::min(kcap, h));
+                rrow += n_opt;
+                for (int o = 0; o < n_opt; o++) rslices += pl.opt_k[pl.opt_base[h] + o];
+            }
+            // one X brings c distinct column spans; they must fit the LDS record budget
+            if ((int64_t)rrow * c > kRecCap) return TRS_ENOSPACE;
+            int64_t xa = 0;
+            while (xa < s.nX) {
+                std::map<std::pair<int, int>, int> seen;
+                std::vector<uint8_t> map;
+                std::vector<uint16_t> spans;
+                int32_t xcount = 0;
+                while (xa + xcount < s.nX) {
+                    const uint16_t *X = &s.X[(xa + xcount) * (c + 1)];
+                    int fresh = 0;
+                    for (int i = 0; i < c; i++)
+                        if (!seen.count({X[i], X[i + 1]})) fresh++;
+                    int ns = (int)seen.size() + fresh;
+                    bool fits = (int64_t)ns * rrow <= kRecCap && ns <= kSpanCap &&
+                                (int64_t)(xcount + 1) * c <= kMapCap;
+                    if (!fits) break;
+                    for (int i = 0; i < c; i++) {
+                        auto key = std::make_pair((int)X[i], (int)X[i + 1]);
+                        auto it = seen.find(key);
+                        int idx;
+                        if (it == seen.end()) {
+                            idx = (int)seen.size();
+                            seen[key] = idx;
+                            spans.push_back(X[i]);
+                            spans.push_back(X[i + 1]);
+                        } else {
+                            idx = it->second;
+                        }
+                        map.push_back((uint8_t)idx);
+                    }
+                    xcount++;
+                    if ((int64_t)xcount * M >= target) break;
+                }
+                if (xcount == 0) return TRS_ENOSPACE;
+                ItemDev it{};
+                it.rank0 = rank_base + xa * SM + pl.y_prefM[sd.yinfo_off + yi];
+                it.combo_off = pl.y_combo[sd.yinfo_off + yi];
+                it.shape = shape_idx;
+                it.yi = (int32_t)yi;
+                it.xa = (int32_t)xa;
+                it.xcount = xcount;
+                it.M = M;
+                it.span_off = (int32_t)(pl.spans.size() / 2);
+                it.nspans = (int32_t)seen.size();
+                it.map_off = (int32_t)pl.spanmap.size();
+                it.rrow = rrow;
+                pl.max_rrow_span = std::max(pl.max_rrow_span, it.nspans * rrow);
+                pl.records += (int64_t)it.nspans * rrow;
+                pl.record_slices += (int64_t)it.nspans * rslices;
+                pl.spans.insert(pl.spans.end(), spans.begin(), spans.end());
+                pl.spanmap.insert(pl.spanmap.end(), map.begin(), map.end());
+                pl.items.push_back(it);
+                xa += xcount;
+            }
+        }
+        if (pl.items.size() > (size_t)1 << 26) return TRS_ENOSPACE;
+        rank_base += s.nX * SM;
+        pl.tile_lookups += s.nX * SM * T;
+        pl.shapes.push_back(sd);
+    }
+    if (rank_base != pl.total) return TRS_EINVAL;            // two counts must agree
+
+    // The uniform grid (Section 3.2): c_u r_u = N, most square, c_u >= r_u, one RS per tile.
+    pl.ru = 1;
+    for (int d = 1; d * d <= N; d++) if (N % d == 0) pl.ru = d;
+    pl.cu = N / pl.ru;
+    pl.n_unif = 0;
+    pl.unif_rs.clear();
+    pl.uniform_rank = -1;
+    if (pl.cu <= W && pl.ru <= H) {
+        for (int j = 0; j < pl.ru; j++)
+            for (int i = 0; i < pl.cu; i++) {
+                pl.unif_rs.push_back((int32_t)((int64_t)i * W / pl.cu));
+                pl.unif_rs.push_back((int32_t)((int64_t)j * H / pl.ru));
+                pl.unif_rs.push_back((int32_t)((int64_t)(i + 1) * W / pl.cu));
+                pl.unif_rs.push_back((int32_t)((int64_t)(j + 1) * H / pl.ru));
+                pl.n_unif++;
+            }
+        for (const auto &sd : pl.shapes) {
+            if (sd.c != pl.cu || sd.r != pl.ru) continue;
+            int64_t xi = -1, yi = -1;
+            for (int64_t q = 0; q < sd.nX && xi < 0; q++) {
+                bool eq = true;
+                for (int i = 0; i <= sd.c && eq; i++)
+                    eq = pl.xtab[sd.x_off + q * (sd.c + 1) + i] == (int64_t)i * W / sd.c;
+                if (eq) xi = q;
+            }
+            for (int64_t q = 0; q < sd.nY && yi < 0; q++) {
+                bool eq = true;
+                for (int j = 0; j <= sd.r && eq; j++)
+                    eq = pl.ytab[sd.y_off + q * (sd.r + 1) + j] == (int64_t)j * H / sd.r;
+                if (eq) yi = q;
+            }
+            if (xi >= 0 && yi >= 0 && pl.y_M[sd.yinfo_off + yi] > 0)
+                pl.uniform_rank = sd.rank_base + xi * sd.SM + pl.y_prefM[sd.yinfo_off + yi];
+        }
+    }
+    return TRS_OK;
+}
+
+trs_status decode_rank(const Plan &pl, int64_t rank, trs_result *o)
+{
+    if (rank < 0 || rank >= pl.total) return TRS_EINVAL;
+    size_t s = 0;
+    while (s + 1 < pl.shapes.size() && pl.shapes[s + 1].rank_base <= rank) s++;
+    const ShapeDev &sd = pl.shapes[s];
+    int64_t rem = rank - sd.rank_base;
+    int64_t xi = rem / sd.SM, r2 = rem % sd.SM;
+    const int64_t *pref = &pl.y_prefM[sd.yinfo_off];
+    int64_t yi = std::upper_bound(pref, pref + sd.nY, r2) - pref - 1;
+    while (yi > 0 && pl.y_M[sd.yinfo_off + yi] == 0) yi--;
+    int64_t m = r2 - pref[yi];
+    const int32_t M = pl.y_M[sd.yinfo_off + yi];
+    const int64_t coff = pl.y_combo[sd.yinfo_off + yi];
+    const uint16_t *X = &pl.xtab[sd.x_off + xi * (sd.c + 1)];
+    const uint16_t *Y = &pl.ytab[sd.y_off + yi * (sd.r + 1)];
+    o->rank = rank;
+    o->tile_cols = sd.c;
+    o->tile_rows = sd.r;
+    for (int i = 0; i <= sd.c; i++) o->col_bd[i] = X[i];
+    for (int j = 0; j <= sd.r; j++) o->row_bd[j] = Y[j];
+    int n = 0;
+    const int Km = pl.Km;
+    for (int t = 0; t < sd.T; t++) {
+        int i = t % sd.c, j = t / sd.c;
+        int h = Y[j + 1] - Y[j];
+        int opt = pl.opt_base[h] + pl.combos[coff + (int64_t)t * M + m];
+        int k = pl.opt_k[opt];
+        const uint16_t *z = &pl.opt_z[(size_t)opt * (Km + 1)];
+        for (int q = 0; q < k; q++) {
+            o->rs[n][0] = X[i];
+            o->rs[n][1] = Y[j] + z[q];
+            o->rs[n][2] = X[i + 1];
+            o->rs[n][3] = Y[j] + z[q + 1];
+            n++;
+        }
+    }
+    o->n_rs = n;
+    o->dtile_used = pl.dt;
+    o->drs_used = pl.dr;
+    o->n_enumerated = pl.total;
+    return TRS_OK;
+}
+
+}  // namespace trs

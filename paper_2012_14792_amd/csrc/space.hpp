@@ -1,0 +1,113 @@
+// Candidate-space plan: host-built tables that let the GPU enumerate every TRS candidate
+// of a frame geometry in canonical rank order, and the device-side views of them.
+//
+// A candidate (Section 1 and Section 2.3 of the paper, with the explicit space of the
+// design notes) is a c x r tile grid with column boundaries X and row boundaries Y, plus,
+// per tile, a slice count k and split offsets Z, with sum of k = N.  For a fixed shape and
+// Y, the list of per-tile choices ("combinations") does not depend on X, so the space is
+// stored as: per shape, the X list and the Y list; per (shape, Y), its combinations, each
+// a vector of per-tile option indices; per tile height h, the option list (k ascending,
+// then Z lexicographic).  Canonical rank = shape base + xi * sum_Y M(Y) + prefix_M(yi) + m.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "trs.h"
+
+namespace trs {
+
+constexpr int kMaxRS = TRS_MAX_RS;
+constexpr int kMaxGrid = 256;        // CTU columns / rows
+constexpr int kRecCap = 2048;        // tile-option records staged in LDS per work item
+constexpr int kMapCap = 2048;        // (X in item) x (tile column) span-map entries per item
+constexpr int kSpanCap = 255;        // distinct column spans per work item
+constexpr int64_t kComboCap = int64_t(1) << 28;   // u16 entries in all combination tables
+constexpr int64_t kSpaceCap = int64_t(1) << 40;
+
+// One tile-grid shape (c, r).
+struct ShapeDev {
+    int32_t c, r, T, kcap;     // kcap = min(Kmax, N - (T - 1)): largest k any tile can take
+    int64_t nX, nY, SM;        // |X|, |Y|, sum over Y of M(Y)
+    int64_t rank_base;         // rank of this shape's first candidate
+    int64_t x_off, y_off;      // u16 offsets of the X and Y tables (rows of c+1 / r+1)
+    int64_t yinfo_off;         // offset into the per-Y arrays
+};
+
+// A unit of GPU work: xcount consecutive X vectors of one (shape, Y), all M combinations.
+struct ItemDev {
+    int64_t rank0;             // rank of (X = xa, Y = yi, m = 0)
+    int64_t combo_off;         // u16 offset of this (shape, Y)'s table, laid out [T][M]
+    int32_t shape, yi, xa, xcount, M;
+    int32_t span_off;          // first (a, b) pair of the item's distinct column spans
+    int32_t nspans;
+    int32_t map_off;           // xcount * c span indices (u8), X-major
+    int32_t rrow;              // records per span: sum over tile rows of usable options
+    int32_t pad;
+};
+
+// Device pointers into the uploaded plan (passed to kernels by value).
+struct SpaceView {
+    const int32_t *colpx, *rowpx;      // pixel prefix sums of CTU widths / heights
+    const int32_t *opt_base;           // [H + 1]: first option of height h
+    const int32_t *opt_kcnt;           // [(H + 1) * (Kmax + 1)]: options of height h with k <= kk
+    const uint8_t *opt_k;              // per option: k
+    const uint16_t *opt_z;             // per option: Kmax + 1 offsets z_0 = 0 .. z_k = h
+    const ShapeDev *shapes;
+    const uint16_t *xtab, *ytab;
+    const int64_t *y_prefM, *y_combo;
+    const int32_t *y_M;
+    const uint16_t *combos;
+    const ItemDev *items;
+    const uint16_t *spans;
+    const uint8_t *spanmap;
+    const int32_t *unif_rs;            // [n_unif * 4]
+    int32_t W, H, N, Km, n_items, n_shapes, n_unif, pad;
+    int64_t total, uniform_rank;
+};
+
+struct Plan {
+    // key
+    int32_t device, width, height, cs, N, Cm, Rm, Km, dtile_req, drs_req, item_target;
+    int64_t budget;
+    // geometry and space
+    int32_t W = 0, H = 0, dt = 0, dr = 0;
+    int64_t total = 0;
+    std::vector<int32_t> colpx, rowpx, opt_base, opt_kcnt;
+    std::vector<uint8_t> opt_k;
+    std::vector<uint16_t> opt_z;
+    std::vector<ShapeDev> shapes;
+    std::vector<uint16_t> xtab, ytab;
+    std::vector<int64_t> y_prefM, y_combo;
+    std::vector<int32_t> y_M;
+    std::vector<uint16_t> combos;
+    std::vector<ItemDev> items;
+    std::vector<uint16_t> spans;
+    std::vector<uint8_t> spanmap;
+    int32_t cu = 0, ru = 0, n_unif = 0;
+    std::vector<int32_t> unif_rs;
+    int64_t uniform_rank = -1;
+    int32_t max_rrow_span = 0;         // largest nspans * rrow over items (LDS records)
+    int64_t tile_lookups = 0, records = 0, record_slices = 0;
+    // device copy
+    void *dblob = nullptr;
+    size_t dbytes = 0;
+    SpaceView view{};
+};
+
+// Validates the geometry/parameters that the space depends on.
+trs_status check_space_args(const trs_frame *f, const trs_search_params *p);
+
+// Ladder rule and |C| without building tables.
+trs_status space_size(int W, int H, const trs_search_params *p, int64_t *n, int32_t *dt,
+                      int32_t *dr);
+
+// Builds the host tables (no device work).
+trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &plan);
+
+// Host decode of a rank.
+trs_status decode_rank(const Plan &plan, int64_t rank, trs_result *out);
+
+}  // namespace trs
