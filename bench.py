@@ -42,6 +42,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=16, help="oracle worker threads (cap)")
     ap.add_argument("--sched-block", type=int, default=0)
     ap.add_argument("--sched-item", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 1 GiB once before timing (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -87,6 +89,14 @@ def main():
     torch.cuda.synchronize()
     log(f"inputs ready: {F} frames {w}x{h} in {time.perf_counter() - t0:.1f} s; "
         f"{stats['candidates']} candidates/frame, {stats['items']} work items")
+
+    if args.copy_probe:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB device-to-device copy done")
 
     part = B.Partitioner(w, h, params)
     outs = torch.empty((F, B.RESULT_BYTES), dtype=torch.uint8, device="cuda")

@@ -112,14 +112,18 @@ typedef struct trs_search_params {
  *                 exact integers) of the chosen partition; ties in Q are broken by smaller
  *                 T~(P), then by smaller rank;
  *   n_enumerated  |C|; n_feasible: candidates passing the area rule;
+ *   n_step2       candidates scored in step 2: a work item whose step-1 minimum already
+ *                 exceeds the Eq. 4 bound cannot hold a step-2 candidate and is skipped;
  *   uniform_rank, t_unif, q_unif: rank and scores of the uniform c_u x r_u grid
  *                 (c_u r_u = N, most square, c_u >= r_u, one RS per tile);
  *   status        TRS_OK or TRS_ENOFEASIBLE;
  *   col_bd/row_bd tile boundaries in CTUs (tile_cols + 1 and tile_rows + 1 entries);
  *   rs[i]         RS rectangles {x0, y0, x1, y1} in CTUs (half open), tiles in raster
- *                 order, top to bottom inside a tile; rs_time[i] its predicted time. */
+ *                 order, top to bottom inside a tile; rs_time[i] its predicted time.
+ * Every byte is written: entries past tile_cols + 1, tile_rows + 1 and n_rs are zero. */
 typedef struct trs_result {
-    int64_t rank, t_min, t_sel, q_sel, n_enumerated, n_feasible, uniform_rank, t_unif, q_unif;
+    int64_t rank, t_min, t_sel, q_sel, n_enumerated, n_feasible, n_step2, uniform_rank, t_unif,
+            q_unif;
     int32_t status, tile_cols, tile_rows, n_rs, dtile_used, drs_used;
     int32_t col_bd[TRS_MAX_RS + 1], row_bd[TRS_MAX_RS + 1];
     int32_t rs[TRS_MAX_RS][4];

@@ -52,7 +52,8 @@ class PlanStats(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int64), ("t_min", ctypes.c_int64), ("t_sel", ctypes.c_int64),
                 ("q_sel", ctypes.c_int64), ("n_enumerated", ctypes.c_int64),
-                ("n_feasible", ctypes.c_int64), ("uniform_rank", ctypes.c_int64),
+                ("n_feasible", ctypes.c_int64), ("n_step2", ctypes.c_int64),
+                ("uniform_rank", ctypes.c_int64),
                 ("t_unif", ctypes.c_int64), ("q_unif", ctypes.c_int64),
                 ("status", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
                 ("tile_rows", ctypes.c_int32), ("n_rs", ctypes.c_int32),
@@ -184,7 +185,8 @@ def result_dict(r: Result) -> dict:
     n = r.n_rs
     return dict(
         status=r.status, rank=r.rank, t_min=r.t_min, t_sel=r.t_sel, q_sel=r.q_sel,
-        n_enumerated=r.n_enumerated, n_feasible=r.n_feasible, uniform_rank=r.uniform_rank,
+        n_enumerated=r.n_enumerated, n_feasible=r.n_feasible, n_step2=r.n_step2,
+        uniform_rank=r.uniform_rank,
         t_unif=r.t_unif, q_unif=r.q_unif, tile_cols=r.tile_cols, tile_rows=r.tile_rows,
         n_rs=n, dtile_used=r.dtile_used, drs_used=r.drs_used,
         col_bd=[r.col_bd[i] for i in range(r.tile_cols + 1)] if r.tile_cols else [],

@@ -179,6 +179,7 @@ k_sat(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restric
         hdr->tmin = kNone;
         hdr->nfeas = 0;
         hdr->pruned = 0;
+        hdr->step2 = 0;
     }
     for (int x = tid; x <= W; x += blockDim.x) satT[x] = satS1[x] = satS2[x] = 0;
     for (int y = wv; y < H; y += nw) {
@@ -442,6 +443,7 @@ k_search(SpaceView sp, const long long *__restrict__ satT, const long long *__re
                 if (key_less(o, b)) b = o;
             }
             part[item] = Partial{b.q, b.t, b.rank, item, b.f};
+            atomicAdd(&hdr->step2, (unsigned long long)total);
         }
     }
 }
@@ -472,6 +474,14 @@ k_final(SpaceView sp, const Partial *__restrict__ part, int n_items, const WsHea
     __shared__ long long redr[NW];
     __shared__ int redf[NW], redi[NW];
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    for (int i = tid; i <= kMaxRS; i += 256) {
+        out->col_bd[i] = 0;
+        out->row_bd[i] = 0;
+    }
+    for (int i = tid; i < kMaxRS; i += 256) {
+        for (int e = 0; e < 4; e++) out->rs[i][e] = 0;
+        out->rs_time[i] = 0;
+    }
     Key2 best{kNone, kNone, LLONG_MAX, -1};
     int bitem = -1;
     for (int i = tid; i < n_items; i += 256) {
@@ -501,6 +511,7 @@ k_final(SpaceView sp, const Partial *__restrict__ part, int n_items, const WsHea
 
     out->n_enumerated = sp.total;
     out->n_feasible = (long long)hdr->nfeas;
+    out->n_step2 = (long long)hdr->step2;
     out->dtile_used = dt;
     out->drs_used = dr;
     out->uniform_rank = sp.uniform_rank;

@@ -12,7 +12,8 @@ struct WsHeader {
     unsigned long long tmin;        // step 1 minimum over feasible candidates
     unsigned long long nfeas;       // feasible candidates counted in step 1
     unsigned long long pruned;      // step-2 work items skipped by their step-1 minimum
-    unsigned long long pad[5];
+    unsigned long long step2;       // candidates scored in step 2
+    unsigned long long pad[4];
 };
 
 // One work item's step-2 winner (q = UINT64_MAX when it has none).
