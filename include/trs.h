@@ -154,6 +154,8 @@ trs_status trs_search_workspace(const trs_frame *frame, const trs_search_params 
  * candidate space, exhaustive and exact.  cost: T~ per CTU (u32); s1, s2: per-CTU luma sums
  * from trs_features; workspace: device, at least trs_search_workspace() bytes, 256-byte
  * aligned, contents need not be initialised; out_dev: device trs_result.
+ * Returns TRS_ENOFEASIBLE (a warning: the output, the uniform partition, is still written)
+ * when no candidate of the space passes the area rule, which depends on the geometry only.
  * Errors: TRS_EINVAL, TRS_ENOSPACE, TRS_EWORKSPACE, TRS_EDEVICE. */
 trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
                       const uint32_t *cost, const uint32_t *s1, const uint64_t *s2,
@@ -166,13 +168,15 @@ trs_status trs_space_size(const trs_frame *frame, const trs_search_params *param
                           int64_t *n, int32_t *dtile, int32_t *drs);
 
 /* Work done by one trs_search for this geometry and these parameters (host only; builds
- * the plan if needed).  candidates = |C|; tile_lookups = sum over candidates of their tile
- * count (each step combines one tile-option record per tile); items = work items (one
- * work-group each); records / record_slices = tile-option records built per step and the
- * slices they sum; table_bytes = size of the device tables.  Errors: as trs_search_workspace. */
+ * the plan if needed).  candidates = |C|; feasible = candidates passing the area rule (the
+ * rule depends only on the geometry, so the plan applies it once and each search scores
+ * only these); tile_lookups = sum over feasible candidates of their tile count; items =
+ * work items (one work-group each); records / record_slices = tile-option records built per
+ * step and the slices they sum; records_max = largest record count of one item;
+ * table_bytes = size of the device tables.  Errors: as trs_search_workspace. */
 typedef struct trs_plan_stats {
-    int64_t candidates, tile_lookups, items, records, record_slices, table_bytes;
-    int32_t dtile, drs;
+    int64_t candidates, feasible, tile_lookups, items, records, record_slices, table_bytes;
+    int32_t dtile, drs, records_max, pad;
 } trs_plan_stats;
 
 trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *params,
@@ -186,7 +190,7 @@ trs_status trs_decode(const trs_frame *frame, const trs_search_params *params, i
                       trs_result *out_host);
 
 /* Kernel timing.  While enabled (on != 0), every trs_search records HIP events on its
- * stream before step 1, between step 1 and step 2, and after step 2.  trs_profile_read
+ * stream around its step-1 kernel and around its step-2 kernel.  trs_profile_read
  * waits for the recorded events, returns the summed milliseconds of the step-1 and step-2
  * kernels and the number of searches timed, and clears the record.  Host only; returns
  * TRS_EDEVICE if an event call fails. */

@@ -43,10 +43,11 @@ class SearchParams(ctypes.Structure):
 
 
 class PlanStats(ctypes.Structure):
-    _fields_ = [("candidates", ctypes.c_int64), ("tile_lookups", ctypes.c_int64),
-                ("items", ctypes.c_int64), ("records", ctypes.c_int64),
-                ("record_slices", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
-                ("dtile", ctypes.c_int32), ("drs", ctypes.c_int32)]
+    _fields_ = [("candidates", ctypes.c_int64), ("feasible", ctypes.c_int64),
+                ("tile_lookups", ctypes.c_int64), ("items", ctypes.c_int64),
+                ("records", ctypes.c_int64), ("record_slices", ctypes.c_int64),
+                ("table_bytes", ctypes.c_int64), ("dtile", ctypes.c_int32), ("drs", ctypes.c_int32),
+                ("records_max", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

@@ -29,12 +29,12 @@ std::map<std::vector<int64_t>, PlanEntry> g_plans;
 // Timing events recorded by trs_search while profiling is on (guarded by g_prof_mu).
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-std::vector<std::array<hipEvent_t, 3>> g_prof_events;
+std::vector<std::array<hipEvent_t, 4>> g_prof_events;
 
 std::vector<int64_t> plan_key(const trs_frame *f, const trs_search_params *p)
 {
     return {f->width, f->height, f->ctu_size, p->n_threads, p->max_tile_cols, p->max_tile_rows,
-            p->max_rs_per_tile, p->dtile, p->drs,
+            p->max_rs_per_tile, p->dtile, p->drs, p->area_k,
             p->space_budget > 0 ? p->space_budget : (int64_t(1) << 24), p->sched_item};
 }
 
@@ -92,8 +92,9 @@ trs_status device_view(PlanEntry &e, trs::SpaceView *view)
     size_t o_yM = add_array(parts, off, pl.y_M);
     size_t o_combos = add_array(parts, off, pl.combos);
     size_t o_items = add_array(parts, off, pl.items);
-    size_t o_spans = add_array(parts, off, pl.spans);
-    size_t o_map = add_array(parts, off, pl.spanmap);
+    size_t o_entf = add_array(parts, off, pl.ent_f);
+    size_t o_entr = add_array(parts, off, pl.ent_rid);
+    size_t o_rdesc = add_array(parts, off, pl.rdesc);
     size_t o_unif = add_array(parts, off, pl.unif_rs);
     const size_t bytes = (off + 255) & ~size_t(255);
     std::vector<char> host(bytes, 0);
@@ -121,8 +122,9 @@ trs_status device_view(PlanEntry &e, trs::SpaceView *view)
     v.y_M = reinterpret_cast<const int32_t *>(b + o_yM);
     v.combos = reinterpret_cast<const uint16_t *>(b + o_combos);
     v.items = reinterpret_cast<const trs::ItemDev *>(b + o_items);
-    v.spans = reinterpret_cast<const uint16_t *>(b + o_spans);
-    v.spanmap = reinterpret_cast<const uint8_t *>(b + o_map);
+    v.ent_f = reinterpret_cast<const uint32_t *>(b + o_entf);
+    v.ent_rid = reinterpret_cast<const uint16_t *>(b + o_entr);
+    v.rdesc = reinterpret_cast<const uint32_t *>(b + o_rdesc);
     v.unif_rs = reinterpret_cast<const int32_t *>(b + o_unif);
     v.W = pl.W;
     v.H = pl.H;
@@ -131,6 +133,10 @@ trs_status device_view(PlanEntry &e, trs::SpaceView *view)
     v.n_items = (int32_t)pl.items.size();
     v.n_shapes = (int32_t)pl.shapes.size();
     v.n_unif = pl.n_unif;
+    v.rec_max = pl.rec_max;
+    v.n_feasible = pl.n_feasible;
+    v.cu = pl.cu;
+    v.ru = pl.ru;
     v.total = pl.total;
     v.uniform_rank = pl.uniform_rank;
     e.dev[dev] = {blob, v};
@@ -222,21 +228,21 @@ trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
     a.s2 = s2;
     a.ws = static_cast<char *>(workspace);
     a.out = out_dev;
-    a.area_k = params->area_k;
     a.lam_num = params->lambda_num < 0 ? -1 : params->lambda_num;
     a.lam_den = params->lambda_den;
     a.block = params->sched_block ? params->sched_block : 256;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (g_prof_on) {
-            std::array<hipEvent_t, 3> ev{};
+            std::array<hipEvent_t, 4> ev{};
             for (auto &x : ev)
                 if (hipEventCreate(&x) != hipSuccess) return TRS_EDEVICE;
             g_prof_events.push_back(ev);
-            for (int i = 0; i < 3; i++) a.ev[i] = ev[i];
+            for (int i = 0; i < 4; i++) a.ev[i] = ev[i];
         }
     }
-    return trs::launch_search(a, stream) == hipSuccess ? TRS_OK : TRS_EDEVICE;
+    if (trs::launch_search(a, stream) != hipSuccess) return TRS_EDEVICE;
+    return a.sp.n_feasible == 0 ? TRS_ENOFEASIBLE : TRS_OK;
 }
 
 void trs_profile_enable(int on)
@@ -253,8 +259,8 @@ trs_status trs_profile_read(double *ms_step1, double *ms_step2, int64_t *searche
     trs_status st = TRS_OK;
     for (auto &ev : g_prof_events) {
         float x = 0, y = 0;
-        if (hipEventSynchronize(ev[2]) != hipSuccess || hipEventElapsedTime(&x, ev[0], ev[1]) != hipSuccess ||
-            hipEventElapsedTime(&y, ev[1], ev[2]) != hipSuccess)
+        if (hipEventSynchronize(ev[3]) != hipSuccess || hipEventElapsedTime(&x, ev[0], ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&y, ev[2], ev[3]) != hipSuccess)
             st = TRS_EDEVICE;
         a += x;
         b += y;
@@ -285,10 +291,12 @@ trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *par
     out->records = pl.records;
     out->record_slices = pl.record_slices;
     out->table_bytes = (int64_t)(pl.combos.size() * 2 + pl.xtab.size() * 2 + pl.ytab.size() * 2 +
-                                 pl.items.size() * sizeof(trs::ItemDev) + pl.spans.size() * 2 +
-                                 pl.spanmap.size() + pl.opt_z.size() * 2);
+                                 pl.items.size() * sizeof(trs::ItemDev) + pl.ent_f.size() * 4 +
+                                 pl.ent_rid.size() * 2 + pl.rdesc.size() * 4 + pl.opt_z.size() * 2);
+    out->feasible = pl.n_feasible;
     out->dtile = pl.dt;
     out->drs = pl.dr;
+    out->records_max = pl.rec_max;
     return TRS_OK;
 }
 

@@ -58,6 +58,15 @@ __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a >
 // Features
 // ---------------------------------------------------------------------------------------
 
+// Work-group index -> item: consecutive items (which share combination tables, spans, or
+// neighbouring CTU rows) go to the same XCD, whose L2 then serves them.  Work-groups are
+// dispatched to the 8 XCDs round-robin.
+__device__ __forceinline__ int xcd_item(int b, int G)
+{
+    const int xcd = b & 7, local = b >> 3, q = G >> 3, rm = G & 7;
+    return xcd * q + min(xcd, rm) + local;
+}
+
 template <int CS>
 __global__ void __launch_bounds__((CS / 8) * 16)
 k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, int W,
@@ -68,7 +77,8 @@ k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, in
     constexpr int CH = CS / 8;           // 8-sample chunks per CTU row
     constexpr int NT = CH * 16;          // threads: CH chunks x 16 row groups
     constexpr int R = CS / 16;           // rows per row group
-    const int cx = blockIdx.x, cy = blockIdx.y, tid = threadIdx.x;
+    const int ctu = xcd_item(blockIdx.x, gridDim.x);
+    const int cy = ctu / W, cx = ctu - cy * W, tid = threadIdx.x;
     const int chunk = tid % CH, grp = tid / CH;
     const int x0 = cx * CS + chunk * 8;
     const int ybase = cy * CS + grp * R;
@@ -76,34 +86,43 @@ k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, in
     if (x0 < w && ybase < h) {
         const int nv = min(8, w - x0);
         const bool has_right = x0 + 8 < w;
+        const int nrow = min(R + 1, h - ybase);         // rows present, incl. the halo row
+        // issue every load of this thread before using any of them
+        uint4 v[R + 1];
+        uint32_t right[R];
+        const uint16_t *row0 = luma + (long long)ybase * stride + x0;
+#pragma unroll
+        for (int r = 0; r <= R; r++)
+            v[r] = r < nrow ? *reinterpret_cast<const uint4 *>(row0 + (long long)r * stride)
+                            : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            right[r] = (r < nrow && has_right) ? (uint32_t)row0[(long long)r * stride + 8] : 0u;
         uint32_t prev[8];
 #pragma unroll
         for (int r = 0; r <= R; r++) {
-            const int y = ybase + r;
-            if (y >= h) break;
-            const uint16_t *row = luma + (long long)y * stride + x0;
-            const uint4 v = *reinterpret_cast<const uint4 *>(row);
-            uint32_t p[8] = {v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16,
-                             v.z & 0xffffu, v.z >> 16, v.w & 0xffffu, v.w >> 16};
-            if (r < R) {
-                const uint32_t right = has_right ? (uint32_t)row[8] : 0u;
+            if (r < nrow) {
+                const uint32_t p[8] = {v[r].x & 0xffffu, v[r].x >> 16, v[r].y & 0xffffu, v[r].y >> 16,
+                                       v[r].z & 0xffffu, v[r].z >> 16, v[r].w & 0xffffu, v[r].w >> 16};
+                if (r < R) {
 #pragma unroll
-                for (int j = 0; j < 8; j++) {
-                    if (j < nv) {
-                        a1 += p[j];
-                        a2 += p[j] * p[j];
-                        if (j + 1 < nv) ag += absdiff(p[j + 1], p[j]);
-                        else if (j == 7 && has_right) ag += absdiff(right, p[7]);
+                    for (int j = 0; j < 8; j++) {
+                        if (j < nv) {
+                            a1 += p[j];
+                            a2 += p[j] * p[j];
+                            if (j + 1 < nv) ag += absdiff(p[j + 1], p[j]);
+                            else if (j == 7 && has_right) ag += absdiff(right[r], p[7]);
+                        }
                     }
                 }
-            }
-            if (r >= 1) {
+                if (r >= 1) {
 #pragma unroll
-                for (int j = 0; j < 8; j++)
-                    if (j < nv) ag += absdiff(p[j], prev[j]);
-            }
+                    for (int j = 0; j < 8; j++)
+                        if (j < nv) ag += absdiff(p[j], prev[j]);
+                }
 #pragma unroll
-            for (int j = 0; j < 8; j++) prev[j] = p[j];
+                for (int j = 0; j < 8; j++) prev[j] = p[j];
+            }
         }
     }
     unsigned long long s2 = a2;
@@ -125,13 +144,12 @@ k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, in
         for (int i = 0; i < NW; i++) { t1 += r1[i]; tg += rg[i]; t2 += r2[i]; }
         const unsigned long long cw = min(CS, w - cx * CS), ch = min(CS, h - cy * CS);
         const unsigned long long n = cw * ch;
-        const int c = cy * W + cx;
-        o_s1[c] = t1;
-        o_s2[c] = t2;
-        o_g[c] = tg;
-        o_tex[c] = (uint32_t)(tg / n);
-        o_mean[c] = (uint32_t)(t1 / n);
-        o_var[c] = (uint32_t)((n * t2 - (unsigned long long)t1 * t1) / (n * n));
+        o_s1[ctu] = t1;
+        o_s2[ctu] = t2;
+        o_g[ctu] = tg;
+        o_tex[ctu] = (uint32_t)(tg / n);
+        o_mean[ctu] = (uint32_t)(t1 / n);
+        o_var[ctu] = (uint32_t)((n * t2 - (unsigned long long)t1 * t1) / (n * n));
     }
 }
 
@@ -175,12 +193,6 @@ k_sat(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restric
 {
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, nw = blockDim.x / kWave;
     const int S = W + 1;
-    if (tid == 0) {
-        hdr->tmin = kNone;
-        hdr->nfeas = 0;
-        hdr->pruned = 0;
-        hdr->step2 = 0;
-    }
     for (int x = tid; x <= W; x += blockDim.x) satT[x] = satS1[x] = satS2[x] = 0;
     for (int y = wv; y < H; y += nw) {
         long long cT = 0, c1 = 0, c2 = 0;
@@ -226,6 +238,65 @@ k_sat(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restric
     }
 }
 
+// The same tables built in LDS (grids with (H+1)(W+1) <= kSatLds), written out once.
+constexpr int kSatLds = 2304;
+
+__global__ void __launch_bounds__(512)
+k_sat_lds(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restrict__ s1,
+          const unsigned long long *__restrict__ s2, long long *satT, long long *satS1,
+          long long *satS2, WsHeader *hdr)
+{
+    __shared__ long long lT[kSatLds], l1[kSatLds], l2[kSatLds];
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, nw = blockDim.x / kWave;
+    const int S = W + 1, n = (H + 1) * S;
+    for (int e = tid; e < n; e += blockDim.x) {
+        const int y = e / S, x = e - y * S;
+        const bool in = x > 0 && y > 0;
+        const int c = (y - 1) * W + (x - 1);
+        lT[e] = in ? (long long)cost[c] : 0;
+        l1[e] = in ? (long long)s1[c] : 0;
+        l2[e] = in ? (long long)s2[c] : 0;
+    }
+    __syncthreads();
+    for (int y = 1 + wv; y <= H; y += nw) {           // rows: one wave per row
+        long long cT = 0, c1 = 0, c2 = 0;
+        for (int xb = 1; xb <= W; xb += kWave) {
+            const int x = xb + lane;
+            const int e = y * S + x;
+            long long vT = x <= W ? lT[e] : 0, v1 = x <= W ? l1[e] : 0, v2 = x <= W ? l2[e] : 0;
+            vT = wave_incl_scan(vT, lane);
+            v1 = wave_incl_scan(v1, lane);
+            v2 = wave_incl_scan(v2, lane);
+            if (x <= W) { lT[e] = vT + cT; l1[e] = v1 + c1; l2[e] = v2 + c2; }
+            cT += shfl64(vT, kWave - 1);
+            c1 += shfl64(v1, kWave - 1);
+            c2 += shfl64(v2, kWave - 1);
+        }
+    }
+    __syncthreads();
+    for (int x = 1 + wv; x <= W; x += nw) {           // columns: one wave per column
+        long long cT = 0, c1 = 0, c2 = 0;
+        for (int yb = 1; yb <= H; yb += kWave) {
+            const int y = yb + lane;
+            const int e = y * S + x;
+            long long vT = y <= H ? lT[e] : 0, v1 = y <= H ? l1[e] : 0, v2 = y <= H ? l2[e] : 0;
+            vT = wave_incl_scan(vT, lane);
+            v1 = wave_incl_scan(v1, lane);
+            v2 = wave_incl_scan(v2, lane);
+            if (y <= H) { lT[e] = vT + cT; l1[e] = v1 + c1; l2[e] = v2 + c2; }
+            cT += shfl64(vT, kWave - 1);
+            c1 += shfl64(v1, kWave - 1);
+            c2 += shfl64(v2, kWave - 1);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < n; e += blockDim.x) {
+        satT[e] = lT[e];
+        satS1[e] = l1[e];
+        satS2[e] = l2[e];
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Search
 // ---------------------------------------------------------------------------------------
@@ -254,14 +325,6 @@ __device__ __forceinline__ int kcnt(const SpaceView &sp, int h, int kk)
     return sp.opt_kcnt[h * (sp.Km + 1) + min(kk, sp.Km)];
 }
 
-// Work-group index -> item: consecutive items (which share combination tables and spans)
-// go to the same XCD, whose L2 then serves them.  Work-groups are dispatched to the 8 XCDs
-// round-robin.
-__device__ __forceinline__ int xcd_item(int b, int G)
-{
-    const int xcd = b & 7, local = b >> 3, q = G >> 3, rm = G & 7;
-    return xcd * q + min(xcd, rm) + local;
-}
 
 struct Key2 {
     unsigned long long q, t;
@@ -276,153 +339,119 @@ __device__ __forceinline__ bool key_less(const Key2 &a, const Key2 &b)
     return a.rank < b.rank;
 }
 
-template <int BS, bool P2>
+// Byte offsets of the search kernels' dynamic LDS arrays (-1: not present).
+struct LdsMap {
+    int recT, recQ, satT, satS1, satS2, bytes;
+};
+
+// One work item per work-group.  Phase 1 builds the item's tile-option records in LDS: for
+// a column span, tile row and (k, split offsets) option, the largest slice time (Eq. 1)
+// and, in step 2, the summed per-slice ceil-SSE (Eq. 2).  Phase 2 scores the item's
+// candidates, one per lane: T~(P) is the max of its tiles' record times, Q(P) the sum of
+// their record sums.  STAGE: the prefix sums the records read are first copied to LDS.
+template <int BS, bool P2, bool STAGE>
 __global__ void __launch_bounds__(BS)
-k_search(SpaceView sp, const long long *__restrict__ satT, const long long *__restrict__ satS1,
-         const long long *__restrict__ satS2, WsHeader *hdr,
-         unsigned long long *__restrict__ item_min, Partial *__restrict__ part, int area_k,
-         int lam_num, int lam_den)
+k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
+         const long long *__restrict__ satS1, const long long *__restrict__ satS2,
+         const WsHeader *__restrict__ hdr, unsigned long long *__restrict__ item_min,
+         Partial *__restrict__ part, int lam_num, int lam_den)
 {
-    __shared__ unsigned long long recT[kRecCap];
-    __shared__ unsigned long long recA[kRecCap];           // A_min | A_max << 32
-    __shared__ unsigned long long recQ[P2 ? kRecCap : 1];
-    __shared__ uint8_t smap[kMapCap];
-    __shared__ int srowoff[kMaxRS + 1];
-    __shared__ int sY[kMaxRS + 1];
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds + L.recT);
+    unsigned long long *recQ = reinterpret_cast<unsigned long long *>(lds + (P2 ? L.recQ : L.recT));
     constexpr int NW = BS / kWave;
     __shared__ unsigned long long redq[NW], redt[NW];
     __shared__ long long redr[NW];
     __shared__ int redf[NW];
 
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int S = sp.W + 1;
+    const long long *sT = satT, *s1t = satS1, *s2t = satS2;
+    if (STAGE) {                       // independent of the item: overlaps its load latency
+        long long *lT = reinterpret_cast<long long *>(lds + L.satT);
+        long long *l1 = reinterpret_cast<long long *>(lds + (P2 ? L.satS1 : L.satT));
+        long long *l2 = reinterpret_cast<long long *>(lds + (P2 ? L.satS2 : L.satT));
+        const int n = S * (sp.H + 1);
+        for (int e = tid; e < n; e += BS) {
+            lT[e] = satT[e];
+            if (P2) {
+                l1[e] = satS1[e];
+                l2[e] = satS2[e];
+            }
+        }
+        sT = lT;
+        s1t = l1;
+        s2t = l2;
+    }
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const ItemDev it = sp.items[item];
-    const ShapeDev sd = sp.shapes[it.shape];
 
     unsigned long long bound = kNone;
     if (P2) {
         const unsigned long long tmin = hdr->tmin;
         if (lam_num >= 0)
             bound = tmin * (unsigned long long)(lam_den + lam_num) / (unsigned long long)lam_den;
-        const unsigned long long imin = item_min[item];
-        if (imin == kNone || imin > bound) {         // nothing here can pass Eq. 4
-            if (tid == 0) {
-                part[item] = Partial{kNone, kNone, LLONG_MAX, item, -1};
-                atomicAdd(&hdr->pruned, 1ull);
-            }
+        if (item_min[item] > bound) {                // nothing here can pass Eq. 4
+            if (tid == 0) part[item] = Partial{kNone, kNone, LLONG_MAX, item, -1, 0, 0};
             return;
         }
     }
+    if (STAGE) __syncthreads();
 
-    const int c = sd.c, r = sd.r, T = sd.T, kcap = sd.kcap;
-    const int S = sp.W + 1;
-    const uint16_t *Yg = sp.ytab + sd.y_off + (long long)it.yi * (r + 1);
-    for (int i = tid; i <= r; i += BS) sY[i] = Yg[i];
-    for (int i = tid; i < it.xcount * c; i += BS) smap[i] = sp.spanmap[it.map_off + i];
-    __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int j = 0; j < r; j++) {
-            srowoff[j] = acc;
-            const int h = sY[j + 1] - sY[j];
-            acc += kcnt(sp, h, min(kcap, h));
-        }
-        srowoff[r] = acc;
-    }
-    __syncthreads();
-
-    // Tile-option records: for (column span s, tile row j, option o) the option's largest
-    // slice time, smallest and largest slice area and (step 2) summed ceil-SSE.
-    const int rrow = it.rrow;
-    const int nrec = it.nspans * rrow;
-    for (int rid = tid; rid < nrec; rid += BS) {
-        const int s = rid / rrow;
-        const int rem = rid - s * rrow;
-        int j = 0;
-        while (j + 1 < r && srowoff[j + 1] <= rem) j++;
-        const int o = rem - srowoff[j];
-        const int xa = sp.spans[2 * (it.span_off + s)];
-        const int xb = sp.spans[2 * (it.span_off + s) + 1];
-        const int y0 = sY[j], h = sY[j + 1] - y0;
-        const int opt = sp.opt_base[h] + o;
+    for (int rid = tid; rid < it.n_rec; rid += BS) {
+        const uint32_t d0 = sp.rdesc[2 * (it.rec_off + rid)];
+        const int opt = (int)sp.rdesc[2 * (it.rec_off + rid) + 1];
+        const int xa = d0 & 511, xb = (d0 >> 9) & 511, y0 = (int)(d0 >> 18);
         const int k = sp.opt_k[opt];
         const uint16_t *z = sp.opt_z + (long long)opt * (sp.Km + 1);
         const unsigned wpx = (unsigned)(sp.colpx[xb] - sp.colpx[xa]);
         unsigned long long tmax = 0, qs = 0;
-        unsigned amin = ~0u, amax = 0;
         for (int q = 0; q < k; q++) {
             const int ya = y0 + z[q], yb = y0 + z[q + 1];
-            const unsigned long long tsum = (unsigned long long)rect(satT, S, xa, ya, xb, yb);
-            const unsigned area = wpx * (unsigned)(sp.rowpx[yb] - sp.rowpx[ya]);
-            tmax = max(tmax, tsum);
-            amin = min(amin, area);
-            amax = max(amax, area);
+            tmax = max(tmax, (unsigned long long)rect(sT, S, xa, ya, xb, yb));
             if (P2) {
-                const unsigned long long s1 = (unsigned long long)rect(satS1, S, xa, ya, xb, yb);
-                const unsigned long long s2 = (unsigned long long)rect(satS2, S, xa, ya, xb, yb);
-                qs += s2 - floor_sq_div(s1, area);
+                const unsigned area = wpx * (unsigned)(sp.rowpx[yb] - sp.rowpx[ya]);
+                const unsigned long long a1 = (unsigned long long)rect(s1t, S, xa, ya, xb, yb);
+                const unsigned long long a2 = (unsigned long long)rect(s2t, S, xa, ya, xb, yb);
+                qs += a2 - floor_sq_div(a1, area);
             }
         }
         recT[rid] = tmax;
-        recA[rid] = (unsigned long long)amin | ((unsigned long long)amax << 32);
         if (P2) recQ[rid] = qs;
     }
     __syncthreads();
 
-    // One candidate per lane: combine the T tile records of combination m for X = xa + xl.
-    const int M = it.M;
-    const int total = it.xcount * M;
-    const uint16_t *__restrict__ cmb = sp.combos + it.combo_off;
-    const float invM = 1.0f / (float)M;
-    const unsigned long long ak = (unsigned long long)area_k;
-    unsigned long long tbest = kNone, cnt = 0;
+    const int n = it.n_ent, T = it.T;
+    const uint16_t *__restrict__ rids = sp.ent_rid + it.rid_off;
+    unsigned long long tbest = kNone;
     Key2 best{kNone, kNone, LLONG_MAX, -1};
-    for (int f = tid; f < total; f += BS) {
-        int xl = (int)((float)f * invM);
-        int m = f - xl * M;
-        if (m < 0) { xl--; m += M; } else if (m >= M) { xl++; m -= M; }
-        const uint8_t *mp = smap + xl * c;
+    for (int e = tid; e < n; e += BS) {
         unsigned long long tmax = 0, qsum = 0;
-        unsigned amin = ~0u, amax = 0;
-        int t = 0;
-        for (int j = 0; j < r; j++) {
-            const int ro = srowoff[j];
-            for (int i = 0; i < c; i++, t++) {
-                const int rid = (int)mp[i] * rrow + ro + (int)cmb[(long long)t * M + m];
-                tmax = max(tmax, recT[rid]);
-                const unsigned long long A = recA[rid];
-                amin = min(amin, (unsigned)A);
-                amax = max(amax, (unsigned)(A >> 32));
-                if (P2) qsum += recQ[rid];
-            }
+#pragma unroll 4
+        for (int t = 0; t < T; t++) {
+            const int rr = rids[t * n + e];
+            tmax = max(tmax, recT[rr]);
+            if (P2) qsum += recQ[rr];
         }
-        const bool feas = area_k == 0 || ak * amin > (unsigned long long)amax;
         if (!P2) {
-            if (feas) {
-                cnt++;
-                tbest = min(tbest, tmax);
-            }
-        } else if (feas && tmax <= bound) {
-            const Key2 cand{qsum, tmax, it.rank0 + (long long)xl * sd.SM + m, f};
+            tbest = min(tbest, tmax);
+        } else if (tmax <= bound && (qsum < best.q || (qsum == best.q && tmax <= best.t))) {
+            const int f = (int)sp.ent_f[it.ent_off + e];
+            const int xl = f / it.M;
+            const Key2 cand{qsum, tmax, it.rank0 + (long long)xl * it.SM + (f - xl * it.M), f};
             if (key_less(cand, best)) best = cand;
         }
     }
-    (void)T;
 
     if (!P2) {
 #pragma unroll
-        for (int m = kWave / 2; m >= 1; m >>= 1) {
-            tbest = min(tbest, shfl_xor64(tbest, m));
-            cnt += shfl_xor64(cnt, m);
-        }
-        if (lane == 0) { redt[wv] = tbest; redq[wv] = cnt; }
+        for (int m = kWave / 2; m >= 1; m >>= 1) tbest = min(tbest, shfl_xor64(tbest, m));
+        if (lane == 0) redt[wv] = tbest;
         __syncthreads();
         if (tid == 0) {
-            unsigned long long bt = kNone, bc = 0;
-            for (int i = 0; i < NW; i++) { bt = min(bt, redt[i]); bc += redq[i]; }
+            unsigned long long bt = kNone;
+            for (int i = 0; i < NW; i++) bt = min(bt, redt[i]);
             item_min[item] = bt;
-            if (bt != kNone) atomicMin(&hdr->tmin, bt);
-            if (bc) atomicAdd(&hdr->nfeas, bc);
         }
     } else {
 #pragma unroll
@@ -442,9 +471,28 @@ k_search(SpaceView sp, const long long *__restrict__ satT, const long long *__re
                 const Key2 o{redq[i], redt[i], redr[i], redf[i]};
                 if (key_less(o, b)) b = o;
             }
-            part[item] = Partial{b.q, b.t, b.rank, item, b.f};
-            atomicAdd(&hdr->step2, (unsigned long long)total);
+            part[item] = Partial{b.q, b.t, b.rank, item, b.f, n, 0};
         }
+    }
+}
+
+// T~min (Eq. 3): the smallest step-1 result over the work items.
+__global__ void __launch_bounds__(1024)
+k_tmin(int n_items, const unsigned long long *__restrict__ item_min, WsHeader *hdr)
+{
+    constexpr int NW = 1024 / kWave;
+    __shared__ unsigned long long rt[NW];
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    unsigned long long t = kNone;
+    for (int i = tid; i < n_items; i += 1024) t = min(t, item_min[i]);
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) t = min(t, shfl_xor64(t, m));
+    if (lane == 0) rt[wv] = t;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long bt = kNone;
+        for (int i = 0; i < NW; i++) bt = min(bt, rt[i]);
+        hdr->tmin = bt;
     }
 }
 
@@ -473,7 +521,13 @@ k_final(SpaceView sp, const Partial *__restrict__ part, int n_items, const WsHea
     __shared__ unsigned long long redq[NW], redt[NW];
     __shared__ long long redr[NW];
     __shared__ int redf[NW], redi[NW];
+    __shared__ int sk[kMaxRS];                       // slices per tile of the winner
+    __shared__ long long ut[kMaxRS], uq[kMaxRS];     // uniform slice scores
+    __shared__ Key2 sbest;
+    __shared__ int sbi;
+    __shared__ unsigned long long redn[NW];
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int S = sp.W + 1;
     for (int i = tid; i <= kMaxRS; i += 256) {
         out->col_bd[i] = 0;
         out->row_bd[i] = 0;
@@ -482,13 +536,23 @@ k_final(SpaceView sp, const Partial *__restrict__ part, int n_items, const WsHea
         for (int e = 0; e < 4; e++) out->rs[i][e] = 0;
         out->rs_time[i] = 0;
     }
+    // uniform grid scores, one slice per thread
+    if (tid < sp.n_unif)
+        score_rect(sp, satT, satS1, satS2, sp.unif_rs[4 * tid], sp.unif_rs[4 * tid + 1],
+                   sp.unif_rs[4 * tid + 2], sp.unif_rs[4 * tid + 3], &ut[tid], &uq[tid]);
+    // step-2 winner over the work items' partials
     Key2 best{kNone, kNone, LLONG_MAX, -1};
     int bitem = -1;
+    unsigned long long scored = 0;
     for (int i = tid; i < n_items; i += 256) {
         const Partial p = part[i];
         const Key2 k{p.q, p.t, p.rank, p.f};
+        scored += (unsigned long long)p.n;
         if (p.q != kNone && key_less(k, best)) { best = k; bitem = p.item; }
     }
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) scored += shfl_xor64(scored, m);
+    if (lane == 0) redn[wv] = scored;
 #pragma unroll
     for (int m = kWave / 2; m >= 1; m >>= 1) {
         Key2 o;
@@ -501,105 +565,155 @@ k_final(SpaceView sp, const Partial *__restrict__ part, int n_items, const WsHea
     }
     if (lane == 0) { redq[wv] = best.q; redt[wv] = best.t; redr[wv] = best.rank; redf[wv] = best.f; redi[wv] = bitem; }
     __syncthreads();
-    if (tid != 0) return;
-    Key2 b{redq[0], redt[0], redr[0], redf[0]};
-    int bi = redi[0];
-    for (int i = 1; i < NW; i++) {
-        const Key2 o{redq[i], redt[i], redr[i], redf[i]};
-        if (key_less(o, b)) { b = o; bi = redi[i]; }
+    if (tid == 0) {
+        Key2 b{redq[0], redt[0], redr[0], redf[0]};
+        int bi = redi[0];
+        for (int i = 1; i < NW; i++) {
+            const Key2 o{redq[i], redt[i], redr[i], redf[i]};
+            if (key_less(o, b)) { b = o; bi = redi[i]; }
+        }
+        sbest = b;
+        sbi = bi;
     }
+    __syncthreads();
+    const Key2 b = sbest;
+    const bool none = sp.n_feasible == 0 || b.q == kNone;  // uniform over the block
+    int ncols, nrows, nrs;
+    if (none) {
+        // no feasible candidate: the uniform grid
+        ncols = sp.n_unif ? sp.cu : 0;
+        nrows = sp.n_unif ? sp.ru : 0;
+        nrs = sp.n_unif;
+        if (tid <= ncols && ncols) out->col_bd[tid] = (int)((long long)tid * sp.W / sp.cu);
+        if (tid <= nrows && nrows) out->row_bd[tid] = (int)((long long)tid * sp.H / sp.ru);
+        if (tid < nrs) {
+            for (int e = 0; e < 4; e++) out->rs[tid][e] = sp.unif_rs[4 * tid + e];
+            out->rs_time[tid] = ut[tid];
+        }
+    } else {
+        const ItemDev it = sp.items[sbi];
+        const ShapeDev sd = sp.shapes[it.shape];
+        const int xl = b.f / it.M, m = b.f - xl * it.M;
+        const uint16_t *X = sp.xtab + sd.x_off + (long long)(it.xa + xl) * (sd.c + 1);
+        const uint16_t *Y = sp.ytab + sd.y_off + (long long)it.yi * (sd.r + 1);
+        ncols = sd.c;
+        nrows = sd.r;
+        if (tid <= sd.c) out->col_bd[tid] = X[tid];
+        if (tid <= sd.r) out->row_bd[tid] = Y[tid];
+        int opt = 0, i = 0, j = 0, h = 0;
+        if (tid < sd.T) {
+            i = tid % sd.c;
+            j = tid / sd.c;
+            h = Y[j + 1] - Y[j];
+            opt = sp.opt_base[h] + sp.combos[it.combo_off + (long long)tid * it.M + m];
+            sk[tid] = sp.opt_k[opt];
+        }
+        __syncthreads();
+        nrs = 0;
+        for (int t = 0; t < sd.T; t++) nrs += sk[t];
+        if (tid < sd.T) {
+            int slot = 0;
+            for (int t = 0; t < tid; t++) slot += sk[t];
+            const uint16_t *z = sp.opt_z + (long long)opt * (sp.Km + 1);
+            for (int q = 0; q < sk[tid]; q++, slot++) {
+                const int y0 = Y[j] + z[q], y1 = Y[j] + z[q + 1];
+                out->rs[slot][0] = X[i];
+                out->rs[slot][1] = y0;
+                out->rs[slot][2] = X[i + 1];
+                out->rs[slot][3] = y1;
+                out->rs_time[slot] = rect(satT, S, X[i], y0, X[i + 1], y1);
+            }
+        }
+    }
+    if (tid == 0) {
+        long long tu = -1, qu = -1;
+        if (sp.n_unif > 0) {
+            tu = 0;
+            qu = 0;
+            for (int q = 0; q < sp.n_unif; q++) { tu = max(tu, ut[q]); qu += uq[q]; }
+        }
+        out->n_enumerated = sp.total;
+        out->n_feasible = sp.n_feasible;
+        unsigned long long n2 = 0;
+        for (int q = 0; q < NW; q++) n2 += redn[q];
+        out->n_step2 = (long long)n2;
+        out->dtile_used = dt;
+        out->drs_used = dr;
+        out->uniform_rank = sp.uniform_rank;
+        out->t_unif = tu;
+        out->q_unif = qu;
+        out->tile_cols = ncols;
+        out->tile_rows = nrows;
+        out->n_rs = nrs;
+        if (none) {
+            out->status = TRS_ENOFEASIBLE;
+            out->rank = sp.uniform_rank;
+            out->t_min = -1;
+            out->t_sel = tu;
+            out->q_sel = qu;
+        } else {
+            out->status = TRS_OK;
+            out->rank = b.rank;
+            out->t_min = (long long)hdr->tmin;
+            out->t_sel = (long long)b.t;
+            out->q_sel = (long long)b.q;
+        }
+    }
+}
 
-    out->n_enumerated = sp.total;
-    out->n_feasible = (long long)hdr->nfeas;
-    out->n_step2 = (long long)hdr->step2;
-    out->dtile_used = dt;
-    out->drs_used = dr;
-    out->uniform_rank = sp.uniform_rank;
-    long long ut = -1, uq = -1;
-    if (sp.n_unif > 0) {
-        ut = 0;
-        uq = 0;
-        for (int i = 0; i < sp.n_unif; i++) {
-            long long t, q;
-            score_rect(sp, satT, satS1, satS2, sp.unif_rs[4 * i], sp.unif_rs[4 * i + 1],
-                       sp.unif_rs[4 * i + 2], sp.unif_rs[4 * i + 3], &t, &q);
-            ut = max(ut, t);
-            uq += q;
+// LDS layout of a search kernel: records and (when staged) the prefix sums.
+LdsMap lds_map(const SpaceView &sp, bool p2, bool stage)
+{
+    LdsMap L{-1, -1, -1, -1, -1, 0};
+    int off = 0;
+    auto take = [&](int bytes) { int at = off; off += (bytes + 15) & ~15; return at; };
+    const int rec = sp.rec_max > 0 ? sp.rec_max : 1;
+    L.recT = take(8 * rec);
+    if (p2) L.recQ = take(8 * rec);
+    if (stage) {
+        const int n = (sp.W + 1) * (sp.H + 1);
+        L.satT = take(8 * n);
+        if (p2) {
+            L.satS1 = take(8 * n);
+            L.satS2 = take(8 * n);
         }
     }
-    out->t_unif = ut;
-    out->q_unif = uq;
-    const int S = sp.W + 1;
-    if (hdr->nfeas == 0 || b.q == kNone) {
-        out->status = TRS_ENOFEASIBLE;
-        out->rank = sp.uniform_rank;
-        out->t_min = -1;
-        out->t_sel = ut;
-        out->q_sel = uq;
-        int cu = 0, ru = 0;
-        for (int i = 0; i < sp.n_unif; i++) {
-            if (sp.unif_rs[4 * i + 1] == 0) cu++;
-            if (sp.unif_rs[4 * i] == 0) ru++;
-        }
-        out->tile_cols = sp.n_unif ? cu : 0;
-        out->tile_rows = sp.n_unif ? ru : 0;
-        out->n_rs = sp.n_unif;
-        for (int i = 0; i < cu; i++) out->col_bd[i] = sp.unif_rs[4 * i];
-        if (cu) out->col_bd[cu] = sp.W;
-        for (int j = 0; j < ru; j++) out->row_bd[j] = sp.unif_rs[4 * (j * cu) + 1];
-        if (ru) out->row_bd[ru] = sp.H;
-        for (int i = 0; i < sp.n_unif; i++) {
-            for (int e = 0; e < 4; e++) out->rs[i][e] = sp.unif_rs[4 * i + e];
-            out->rs_time[i] = rect(satT, S, sp.unif_rs[4 * i], sp.unif_rs[4 * i + 1],
-                                   sp.unif_rs[4 * i + 2], sp.unif_rs[4 * i + 3]);
-        }
-        return;
+    L.bytes = off;
+    return L;
+}
+
+constexpr int kStageLimit = 24 * 1024;   // prefix sums copied to LDS only up to this size
+
+template <int BS, bool P2>
+void launch_pass(const SearchArgs &a, const long long *satT, const long long *satS1,
+                 const long long *satS2, WsHeader *hdr, unsigned long long *imin, Partial *part,
+                 hipStream_t s)
+{
+    const int G = a.sp.n_items;
+    const int satb = 8 * (a.sp.W + 1) * (a.sp.H + 1) * (P2 ? 3 : 1);
+    if (satb <= kStageLimit) {
+        const LdsMap L = lds_map(a.sp, P2, true);
+        hipLaunchKernelGGL((k_search<BS, P2, true>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, satT,
+                           satS1, satS2, hdr, imin, part, a.lam_num, a.lam_den);
+    } else {
+        const LdsMap L = lds_map(a.sp, P2, false);
+        hipLaunchKernelGGL((k_search<BS, P2, false>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, satT,
+                           satS1, satS2, hdr, imin, part, a.lam_num, a.lam_den);
     }
-    out->status = TRS_OK;
-    out->rank = b.rank;
-    out->t_min = (long long)hdr->tmin;
-    out->t_sel = (long long)b.t;
-    out->q_sel = (long long)b.q;
-    const ItemDev it = sp.items[bi];
-    const ShapeDev sd = sp.shapes[it.shape];
-    const int xl = b.f / it.M, m = b.f % it.M;
-    const uint16_t *X = sp.xtab + sd.x_off + (long long)(it.xa + xl) * (sd.c + 1);
-    const uint16_t *Y = sp.ytab + sd.y_off + (long long)it.yi * (sd.r + 1);
-    out->tile_cols = sd.c;
-    out->tile_rows = sd.r;
-    for (int i = 0; i <= sd.c; i++) out->col_bd[i] = X[i];
-    for (int j = 0; j <= sd.r; j++) out->row_bd[j] = Y[j];
-    int n = 0;
-    for (int t = 0; t < sd.T; t++) {
-        const int i = t % sd.c, j = t / sd.c;
-        const int h = Y[j + 1] - Y[j];
-        const int opt = sp.opt_base[h] + sp.combos[it.combo_off + (long long)t * it.M + m];
-        const int k = sp.opt_k[opt];
-        const uint16_t *z = sp.opt_z + (long long)opt * (sp.Km + 1);
-        for (int q = 0; q < k; q++) {
-            out->rs[n][0] = X[i];
-            out->rs[n][1] = Y[j] + z[q];
-            out->rs[n][2] = X[i + 1];
-            out->rs[n][3] = Y[j] + z[q + 1];
-            out->rs_time[n] = rect(satT, S, X[i], Y[j] + z[q], X[i + 1], Y[j] + z[q + 1]);
-            n++;
-        }
-    }
-    out->n_rs = n;
 }
 
 template <int BS>
 hipError_t launch_passes(const SearchArgs &a, long long *satT, long long *satS1, long long *satS2,
                          WsHeader *hdr, unsigned long long *imin, Partial *part, hipStream_t s)
 {
-    const int G = a.sp.n_items;
+    const bool any = a.sp.n_items > 0;
     if (a.ev[0] && hipEventRecord(a.ev[0], s) != hipSuccess) return hipErrorUnknown;
-    hipLaunchKernelGGL((k_search<BS, false>), dim3(G), dim3(BS), 0, s, a.sp, satT, satS1, satS2,
-                       hdr, imin, part, a.area_k, a.lam_num, a.lam_den);
+    if (any) launch_pass<BS, false>(a, satT, satS1, satS2, hdr, imin, part, s);
     if (a.ev[1] && hipEventRecord(a.ev[1], s) != hipSuccess) return hipErrorUnknown;
-    hipLaunchKernelGGL((k_search<BS, true>), dim3(G), dim3(BS), 0, s, a.sp, satT, satS1, satS2,
-                       hdr, imin, part, a.area_k, a.lam_num, a.lam_den);
+    if (any) hipLaunchKernelGGL(k_tmin, dim3(1), dim3(1024), 0, s, a.sp.n_items, imin, hdr);
     if (a.ev[2] && hipEventRecord(a.ev[2], s) != hipSuccess) return hipErrorUnknown;
+    if (any) launch_pass<BS, true>(a, satT, satS1, satS2, hdr, imin, part, s);
+    if (a.ev[3] && hipEventRecord(a.ev[3], s) != hipSuccess) return hipErrorUnknown;
     return hipGetLastError();
 }
 
@@ -623,8 +737,8 @@ WsLayout ws_layout(const Plan &pl)
 hipError_t launch_features(int w, int h, int cs, const uint16_t *luma, int64_t stride,
                            const trs_feat &o, hipStream_t s)
 {
-    const dim3 grid((w + cs - 1) / cs, (h + cs - 1) / cs);
-    const int W = grid.x;
+    const int W = (w + cs - 1) / cs;
+    const dim3 grid(W * ((h + cs - 1) / cs));
     switch (cs) {
     case 128:
         hipLaunchKernelGGL(k_features<128>, grid, dim3(256), 0, s, luma, (long long)stride, w, h, W,
@@ -658,8 +772,12 @@ hipError_t launch_search(const SearchArgs &a, hipStream_t s)
     auto *satS2 = reinterpret_cast<long long *>(a.ws + a.lay.satS2);
     auto *imin = reinterpret_cast<unsigned long long *>(a.ws + a.lay.item_min);
     auto *part = reinterpret_cast<Partial *>(a.ws + a.lay.partial);
-    hipLaunchKernelGGL(k_sat, dim3(1), dim3(256), 0, s, a.sp.W, a.sp.H, a.cost, a.s1,
-                       (const unsigned long long *)a.s2, satT, satS1, satS2, hdr);
+    if ((a.sp.W + 1) * (a.sp.H + 1) <= kSatLds)
+        hipLaunchKernelGGL(k_sat_lds, dim3(1), dim3(512), 0, s, a.sp.W, a.sp.H, a.cost, a.s1,
+                           (const unsigned long long *)a.s2, satT, satS1, satS2, hdr);
+    else
+        hipLaunchKernelGGL(k_sat, dim3(1), dim3(256), 0, s, a.sp.W, a.sp.H, a.cost, a.s1,
+                           (const unsigned long long *)a.s2, satT, satS1, satS2, hdr);
     hipError_t e;
     switch (a.block) {
     case 64: e = launch_passes<64>(a, satT, satS1, satS2, hdr, imin, part, s); break;

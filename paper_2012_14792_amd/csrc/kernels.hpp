@@ -10,17 +10,15 @@ namespace trs {
 // Search workspace header (device), followed by the SATs and per-item arrays.
 struct WsHeader {
     unsigned long long tmin;        // step 1 minimum over feasible candidates
-    unsigned long long nfeas;       // feasible candidates counted in step 1
-    unsigned long long pruned;      // step-2 work items skipped by their step-1 minimum
-    unsigned long long step2;       // candidates scored in step 2
-    unsigned long long pad[4];
+    unsigned long long pad[7];
 };
 
-// One work item's step-2 winner (q = UINT64_MAX when it has none).
+// One work item's step-2 winner (q = UINT64_MAX when it has none) and the number of
+// candidates it scored in step 2 (0 when skipped).
 struct Partial {
     unsigned long long q, t;
     long long rank;
-    int32_t item, f;
+    int32_t item, f, n, pad;
 };
 
 struct WsLayout {
@@ -36,11 +34,10 @@ struct SearchArgs {
     char *ws;
     WsLayout lay;
     trs_result *out;
-    int area_k;
     int lam_num, lam_den;             // lam_num < 0: infinite
     int block;                        // work-group size of the search kernels
     int dt, dr;
-    hipEvent_t ev[3];                 // optional timing events (all null when not profiling)
+    hipEvent_t ev[4];                 // optional timing events (all null when not profiling)
 };
 
 hipError_t launch_features(int w, int h, int cs, const uint16_t *luma, int64_t stride,

@@ -276,7 +276,7 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
 
     // Combination tables per (shape, Y), in canonical order.
     int64_t rank_base = 0;
-    const int64_t target = p->sched_item > 0 ? p->sched_item : 4096;
+    const int64_t target = p->sched_item > 0 ? p->sched_item : 1024;
     for (auto &s : sh) {
         const int c = s.c, r = s.r, T = c * r;
         const int kcap = std::min(Km, N - (T - 1));
@@ -371,78 +371,153 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
         pl.ytab.insert(pl.ytab.end(), s.Y.begin(), s.Y.end());
         const int32_t shape_idx = (int32_t)pl.shapes.size();
 
-        // Work items: consecutive X vectors of one Y, sized by the candidate target and by
-        // the LDS record / span-map capacities.
+        // Work items.  Every candidate of (shape, Y) is tested against the area rule here,
+        // once per geometry; the feasible ones are grouped into items of about `target`
+        // candidates, each with the tile-option records its candidates reference.
         for (int64_t yi = 0; yi < s.nY; yi++) {
             const int32_t M = pl.y_M[sd.yinfo_off + yi];
             if (!M) continue;
             const uint16_t *Y = &s.Y[yi * (r + 1)];
-            int rrow = 0, rslices = 0;
+            const uint16_t *cmb = &pl.combos[pl.y_combo[sd.yinfo_off + yi]];
+            std::vector<int> rowoff(r + 1, 0);
             for (int j = 0; j < r; j++) {
                 int h = Y[j + 1] - Y[j];
-                int n_opt = kcnt(h, std::min(kcap, h));
-                rrow += n_opt;
-                for (int o = 0; o < n_opt; o++) rslices += pl.opt_k[pl.opt_base[h] + o];
+                rowoff[j + 1] = rowoff[j] + kcnt(h, std::min(kcap, h));
             }
-            // one X brings c distinct column spans; they must fit the LDS record budget
-            if ((int64_t)rrow * c > kRecCap) return TRS_ENOSPACE;
-            int64_t xa = 0;
-            while (xa < s.nX) {
-                std::map<std::pair<int, int>, int> seen;
-                std::vector<uint8_t> map;
-                std::vector<uint16_t> spans;
-                int32_t xcount = 0;
-                while (xa + xcount < s.nX) {
-                    const uint16_t *X = &s.X[(xa + xcount) * (c + 1)];
-                    int fresh = 0;
-                    for (int i = 0; i < c; i++)
-                        if (!seen.count({X[i], X[i + 1]})) fresh++;
-                    int ns = (int)seen.size() + fresh;
-                    bool fits = (int64_t)ns * rrow <= kRecCap && ns <= kSpanCap &&
-                                (int64_t)(xcount + 1) * c <= kMapCap;
-                    if (!fits) break;
-                    for (int i = 0; i < c; i++) {
-                        auto key = std::make_pair((int)X[i], (int)X[i + 1]);
-                        auto it = seen.find(key);
-                        int idx;
-                        if (it == seen.end()) {
-                            idx = (int)seen.size();
-                            seen[key] = idx;
-                            spans.push_back(X[i]);
-                            spans.push_back(X[i + 1]);
-                        } else {
-                            idx = it->second;
-                        }
-                        map.push_back((uint8_t)idx);
+            const int rrow = rowoff[r];
+            // pixel heights of the smallest / largest slice of each (tile row, option)
+            std::vector<uint64_t> hmn(rrow), hmx(rrow);
+            std::vector<int32_t> optg(rrow), optk(rrow);
+            for (int j = 0; j < r; j++) {
+                int h = Y[j + 1] - Y[j];
+                for (int o = 0; o < rowoff[j + 1] - rowoff[j]; o++) {
+                    int opt = pl.opt_base[h] + o;
+                    int k = pl.opt_k[opt];
+                    const uint16_t *z = &pl.opt_z[(size_t)opt * (Km + 1)];
+                    uint64_t lo = UINT64_MAX, hi = 0;
+                    for (int q = 0; q < k; q++) {
+                        uint64_t px = (uint64_t)(pl.rowpx[Y[j] + z[q + 1]] - pl.rowpx[Y[j] + z[q]]);
+                        lo = std::min(lo, px);
+                        hi = std::max(hi, px);
                     }
-                    xcount++;
-                    if ((int64_t)xcount * M >= target) break;
+                    hmn[rowoff[j] + o] = lo;
+                    hmx[rowoff[j] + o] = hi;
+                    optg[rowoff[j] + o] = opt;
+                    optk[rowoff[j] + o] = k;
                 }
-                if (xcount == 0) return TRS_ENOSPACE;
+            }
+            // open item
+            std::vector<uint32_t> cur_f;
+            std::vector<uint16_t> cur_rid;             // entry-major while building
+            std::vector<uint32_t> cur_desc;
+            std::vector<std::pair<int, int>> cur_spans;
+            std::vector<int32_t> remap;               // span * rrow + rowoff[j] + o -> record
+            int64_t cur_xa = -1;
+            int64_t cur_slices = 0;
+            auto close_item = [&]() {
+                if (cur_f.empty()) return;
+                const int n = (int)cur_f.size();
                 ItemDev it{};
-                it.rank0 = rank_base + xa * SM + pl.y_prefM[sd.yinfo_off + yi];
+                it.rank0 = rank_base + cur_xa * SM + pl.y_prefM[sd.yinfo_off + yi];
                 it.combo_off = pl.y_combo[sd.yinfo_off + yi];
+                it.SM = SM;
+                it.y_row = sd.y_off + yi * (r + 1);
+                it.ent_off = (int64_t)pl.ent_f.size();
+                it.rid_off = (int64_t)pl.ent_rid.size();
+                it.rec_off = (int64_t)(pl.rdesc.size() / 2);
                 it.shape = shape_idx;
                 it.yi = (int32_t)yi;
-                it.xa = (int32_t)xa;
-                it.xcount = xcount;
+                it.xa = (int32_t)cur_xa;
                 it.M = M;
-                it.span_off = (int32_t)(pl.spans.size() / 2);
-                it.nspans = (int32_t)seen.size();
-                it.map_off = (int32_t)pl.spanmap.size();
-                it.rrow = rrow;
-                pl.max_rrow_span = std::max(pl.max_rrow_span, it.nspans * rrow);
-                pl.records += (int64_t)it.nspans * rrow;
-                pl.record_slices += (int64_t)it.nspans * rslices;
-                pl.spans.insert(pl.spans.end(), spans.begin(), spans.end());
-                pl.spanmap.insert(pl.spanmap.end(), map.begin(), map.end());
+                it.n_ent = n;
+                it.n_rec = (int32_t)(cur_desc.size() / 2);
+                it.c = c;
+                it.r = r;
+                it.T = T;
+                pl.ent_f.insert(pl.ent_f.end(), cur_f.begin(), cur_f.end());
+                const size_t base = pl.ent_rid.size();
+                pl.ent_rid.resize(base + (size_t)n * T);
+                for (int e = 0; e < n; e++)
+                    for (int t = 0; t < T; t++) pl.ent_rid[base + (size_t)t * n + e] = cur_rid[(size_t)e * T + t];
+                pl.rdesc.insert(pl.rdesc.end(), cur_desc.begin(), cur_desc.end());
                 pl.items.push_back(it);
-                xa += xcount;
+                pl.rec_max = std::max(pl.rec_max, it.n_rec);
+                pl.records += it.n_rec;
+                pl.record_slices += cur_slices;
+                pl.tile_lookups += (int64_t)n * T;
+                pl.n_feasible += n;
+                cur_f.clear();
+                cur_rid.clear();
+                cur_desc.clear();
+                cur_spans.clear();
+                remap.clear();
+                cur_xa = -1;
+                cur_slices = 0;
+            };
+            std::vector<uint64_t> wpx(c);
+            std::vector<int> sidx(c), tcol(T), trow(T);
+            for (int t = 0; t < T; t++) { tcol[t] = t % c; trow[t] = t / c; }
+            for (int64_t xi = 0; xi < s.nX; xi++) {
+                const uint16_t *X = &s.X[xi * (c + 1)];
+                for (int i = 0; i < c; i++) wpx[i] = (uint64_t)(pl.colpx[X[i + 1]] - pl.colpx[X[i]]);
+                bool have_sidx = false;
+                for (int32_t m = 0; m < M; m++) {
+                    uint64_t amin = UINT64_MAX, amax = 0;
+                    for (int t = 0; t < T; t++) {
+                        const int ro = rowoff[trow[t]] + cmb[(size_t)t * M + m];
+                        amin = std::min(amin, wpx[tcol[t]] * hmn[ro]);
+                        amax = std::max(amax, wpx[tcol[t]] * hmx[ro]);
+                    }
+                    if (p->area_k != 0 && !((uint64_t)p->area_k * amin > amax)) continue;
+                    if (!cur_f.empty() && ((int64_t)cur_desc.size() / 2 + T > kRecCap ||
+                                           (int)cur_spans.size() + c > kSpanCap ||
+                                           (xi - cur_xa + 1) * (int64_t)M > INT32_MAX)) {
+                        close_item();
+                        have_sidx = false;
+                    }
+                    if (cur_f.empty()) {
+                        cur_xa = xi;
+                        have_sidx = false;
+                    }
+                    if (!have_sidx) {
+                        for (int i = 0; i < c; i++) {
+                            std::pair<int, int> key(X[i], X[i + 1]);
+                            int idx = -1;
+                            for (size_t q = 0; q < cur_spans.size(); q++)
+                                if (cur_spans[q] == key) { idx = (int)q; break; }
+                            if (idx < 0) {
+                                idx = (int)cur_spans.size();
+                                cur_spans.push_back(key);
+                                remap.resize(cur_spans.size() * (size_t)rrow, -1);
+                            }
+                            sidx[i] = idx;
+                        }
+                        have_sidx = true;
+                    }
+                    for (int t = 0; t < T; t++) {
+                        const int ro = rowoff[trow[t]] + cmb[(size_t)t * M + m];
+                        const size_t dense = (size_t)sidx[tcol[t]] * rrow + ro;
+                        if (remap[dense] < 0) {
+                            remap[dense] = (int32_t)(cur_desc.size() / 2);
+                            const int i = tcol[t];
+                            cur_desc.push_back((uint32_t)X[i] | ((uint32_t)X[i + 1] << 9) |
+                                               ((uint32_t)Y[trow[t]] << 18));
+                            cur_desc.push_back((uint32_t)optg[ro]);
+                            cur_slices += optk[ro];
+                        }
+                        cur_rid.push_back((uint16_t)remap[dense]);
+                    }
+                    cur_f.push_back((uint32_t)((xi - cur_xa) * M + m));
+                    if ((int64_t)cur_f.size() >= target) {
+                        close_item();
+                        have_sidx = false;
+                    }
+                }
             }
+            close_item();
         }
         if (pl.items.size() > (size_t)1 << 26) return TRS_ENOSPACE;
         rank_base += s.nX * SM;
-        pl.tile_lookups += s.nX * SM * T;
         pl.shapes.push_back(sd);
     }
     if (rank_base != pl.total) return TRS_EINVAL;            // two counts must agree

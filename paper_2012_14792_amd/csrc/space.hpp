@@ -22,7 +22,6 @@ namespace trs {
 constexpr int kMaxRS = TRS_MAX_RS;
 constexpr int kMaxGrid = 256;        // CTU columns / rows
 constexpr int kRecCap = 2048;        // tile-option records staged in LDS per work item
-constexpr int kMapCap = 2048;        // (X in item) x (tile column) span-map entries per item
 constexpr int kSpanCap = 255;        // distinct column spans per work item
 constexpr int64_t kComboCap = int64_t(1) << 28;   // u16 entries in all combination tables
 constexpr int64_t kSpaceCap = int64_t(1) << 40;
@@ -36,16 +35,21 @@ struct ShapeDev {
     int64_t yinfo_off;         // offset into the per-Y arrays
 };
 
-// A unit of GPU work: xcount consecutive X vectors of one (shape, Y), all M combinations.
+// A unit of GPU work: area-feasible candidates of one (shape, Y), from X = xa onwards.
+// The area rule depends only on the geometry, so it is applied when the plan is built and
+// an item lists only the candidates that pass it.  Entry e of the item is candidate
+// f = (x - xa) * M + m; its tile t uses tile-option record ent_rid[rid_off + t * n_ent + e];
+// record i of the item is described by rdesc[2 * (rec_off + i)]: word 0 = column span start
+// | span end << 9 | tile-row start << 18 (CTUs), word 1 = option index.
 struct ItemDev {
     int64_t rank0;             // rank of (X = xa, Y = yi, m = 0)
-    int64_t combo_off;         // u16 offset of this (shape, Y)'s table, laid out [T][M]
-    int32_t shape, yi, xa, xcount, M;
-    int32_t span_off;          // first (a, b) pair of the item's distinct column spans
-    int32_t nspans;
-    int32_t map_off;           // xcount * c span indices (u8), X-major
-    int32_t rrow;              // records per span: sum over tile rows of usable options
-    int32_t pad;
+    int64_t combo_off;         // u16 offset of this (shape, Y)'s combination table, [T][M]
+    int64_t SM;                // rank stride between consecutive X: sum over Y of M(Y)
+    int64_t y_row;             // u16 offset of this item's Y vector (r + 1 entries)
+    int64_t ent_off;           // first entry in ent_f
+    int64_t rid_off;           // first record index in ent_rid
+    int64_t rec_off;           // first record descriptor
+    int32_t shape, yi, xa, M, n_ent, n_rec, c, r, T, pad;
 };
 
 // Device pointers into the uploaded plan (passed to kernels by value).
@@ -61,11 +65,14 @@ struct SpaceView {
     const int32_t *y_M;
     const uint16_t *combos;
     const ItemDev *items;
-    const uint16_t *spans;
-    const uint8_t *spanmap;
+    const uint32_t *ent_f;             // per entry: (x - xa) * M + m
+    const uint16_t *ent_rid;           // per item [T][n_ent] record indices
+    const uint32_t *rdesc;             // per record: two words (see ItemDev)
     const int32_t *unif_rs;            // [n_unif * 4]
     int32_t W, H, N, Km, n_items, n_shapes, n_unif, pad;
-    int64_t total, uniform_rank;
+    int32_t cu, ru;                    // uniform grid shape
+    int32_t rec_max, pad2;             // largest per-item record count
+    int64_t total, uniform_rank, n_feasible;
 };
 
 struct Plan {
@@ -84,12 +91,14 @@ struct Plan {
     std::vector<int32_t> y_M;
     std::vector<uint16_t> combos;
     std::vector<ItemDev> items;
-    std::vector<uint16_t> spans;
-    std::vector<uint8_t> spanmap;
+    std::vector<uint32_t> ent_f;
+    std::vector<uint16_t> ent_rid;
+    std::vector<uint32_t> rdesc;
     int32_t cu = 0, ru = 0, n_unif = 0;
     std::vector<int32_t> unif_rs;
     int64_t uniform_rank = -1;
-    int32_t max_rrow_span = 0;         // largest nspans * rrow over items (LDS records)
+    int32_t rec_max = 0;               // largest record count of an item (LDS records)
+    int64_t n_feasible = 0;            // area-feasible candidates
     int64_t tile_lookups = 0, records = 0, record_slices = 0;
     // device copy
     void *dblob = nullptr;
