@@ -23,7 +23,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12      # 32-bit VALU lane-ops: CUs x lanes/clk x clock
+PEAK_ALU_TOPS = round(256 * 64 * 2.4e9 / 1e12, 2)   # 32-bit VALU lane-ops: CUs x lanes/clk x clock
+PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE on this workload, scaled by the
+# copy-kernel calibration; None where the kernel changed since the counters were taken.
+TRAFFIC = {}
 METRIC = "4K frames partitioned/s + TRS candidates scored/s (1 GPU, bit-exact vs oracle)"
 
 
@@ -105,37 +109,86 @@ def main():
         for f in range(F):
             part.enqueue(luma[f], prev[f], out=outs[f])
 
-    for _ in range(args.warmup):
+    # warm up eagerly (builds and uploads the plan), then capture one step in a HIP graph
+    for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            step()
+    torch.cuda.current_stream().wait_stream(cap)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps), step captured as a graph of {F} frames")
 
-    B.trs_profile_enable(True)
+    # ---- timed region: K graph replays, one per step ---------------------------------------
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        graph.replay()
     torch.cuda.synchronize()
-    t_end = time.perf_counter()
+    elapsed = time.perf_counter() - t_start
+    fps = F * args.steps / elapsed
+    log(f"timed {args.steps} graph replays in {elapsed:.3f} s: {fps:.1f} frames/s")
+
+    # ---- eager steps with HIP events around each kernel of interest ------------------------
+    # (events on the stream the kernels run on: torch's current stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(F)]
+    B.trs_profile_enable(True)
+    feat_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for f in range(F):
+            ev[f][0].record()
+            B.trs_features(frame, luma[f], part.feats)
+            ev[f][1].record()
+            B.trs_cost_map(frame, part.feats["tex"], prev[f], part.blend, part.cost, part.flags)
+            B.trs_search(frame, params, part.cost, part.feats["s1"], part.feats["s2"], part.ws, outs[f])
+        torch.cuda.synchronize()
+        feat_ms += sum(a.elapsed_time(b) for a, b in ev)
+    eager_elapsed = time.perf_counter() - t0
     B.trs_profile_enable(False)
     ms1, ms2, n_search = B.trs_profile_read()
-    elapsed = t_end - t_start
-    fps = F * args.steps / elapsed
-    log(f"timed {args.steps} steps in {elapsed:.3f} s: {fps:.1f} frames/s")
+    n_launch = F * args.steps
+    avg_feat, avg1, avg2 = feat_ms / n_launch, ms1 / max(n_search, 1), ms2 / max(n_search, 1)
+    res_all = [B.result_dict(B.Result.from_buffer_copy(bytes(outs[f].cpu().numpy().tobytes())))
+               for f in range(F)]
+    step2_frac = sum(r["n_step2"] for r in res_all) / max(1, sum(r["n_feasible"] for r in res_all))
+    log(f"eager: {n_launch / eager_elapsed:.1f} frames/s; kernel ms features {avg_feat:.4f} "
+        f"step1 {avg1:.4f} step2 {avg2:.4f}")
 
-    # ---- roofline of the dominant kernel (step 1 or step 2 of the search) -----------------
-    avg1, avg2 = ms1 / max(n_search, 1), ms2 / max(n_search, 1)
-    # algorithmic 32-bit lane-ops of step 1 per launch: per candidate 5 per tile record
-    # (64-bit max, 32-bit min, 32-bit max) + 8 (area test, minimum, count); per record slice
-    # 12 (rectangle sum, area, extrema)
-    ops1 = 5 * stats["tile_lookups"] + 8 * stats["candidates"] + 12 * stats["record_slices"]
-    dominant = "k_search<256, false> (step 1)" if avg1 >= avg2 else "k_search<256, true> (step 2)"
-    achieved = ops1 / (avg1 * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_ALU_TOPS, 2),
-                "unit": "Tops/s", "frac": round(achieved / PEAK_ALU_TOPS, 4), "traffic": None,
-                "kernel": "k_search<256, false> (step 1)", "avg_ms": round(avg1, 5),
-                "ops_per_launch": ops1, "dominant": dominant,
-                "step2_avg_ms": round(avg2, 5)}
+    # ---- roofline of each measured kernel; the longest one is reported as dominant ---------
+    # features: HBM bytes per launch = every luma sample once + the per-CTU outputs
+    feat_bytes = 2 * w * h + W * H * (5 * 4 + 8)
+    # step 1: per feasible candidate one 64-bit max per tile (3 lane-ops) and a 64-bit
+    # minimum (3); per record slice one rectangle sum and max (10)
+    ops1 = 3 * stats["tile_lookups"] + 3 * stats["feasible"] + 10 * stats["record_slices"]
+    # step 2 (work items not skipped by the Eq. 4 bound): per candidate and tile a 64-bit
+    # max and add (5); per candidate the bound test and key compare (6); per record slice
+    # three rectangle sums, the exact floor(S1^2 / n) and the sums (40)
+    ops2 = step2_frac * (5 * stats["tile_lookups"] + 6 * stats["feasible"] + 40 * stats["record_slices"])
+    kernels = {
+        "k_features<128>": {"bound": "hbm", "avg_ms": avg_feat, "work": feat_bytes, "peak": PEAK_HBM_GBS,
+                            "unit": "GB/s", "scale": 1e9},
+        "k_search<256, false> (step 1)": {"bound": "alu", "avg_ms": avg1, "work": ops1,
+                                          "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
+        "k_search<256, true> (step 2)": {"bound": "alu", "avg_ms": avg2, "work": ops2,
+                                         "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
+    }
+    table = {}
+    for name, k in kernels.items():
+        ach = k["work"] / (k["avg_ms"] * 1e-3) / k["scale"] if k["avg_ms"] > 0 else 0.0
+        table[name] = {"bound": k["bound"], "achieved": round(ach, 3), "peak": k["peak"], "unit": k["unit"],
+                       "frac": round(ach / k["peak"], 4), "avg_ms": round(k["avg_ms"], 5),
+                       "work_per_launch": int(k["work"])}
+    dom = max(kernels, key=lambda n: kernels[n]["avg_ms"])
+    roofline = dict(table[dom])
+    roofline["kernel"] = dom
+    roofline["traffic"] = TRAFFIC.get(dom)
 
     # ---- CPU oracle on a bounded sample, on the host's cores ------------------------------
     cpu = None
@@ -184,13 +237,19 @@ def main():
         "config": {"workload": f"4K sequence: {F} frames 3840x2160 10-bit, CTU 128 (30x17), "
                                f"N=8 slices, tiles <= 6x4, <= 4 slices/tile, lambda=1/10, "
                                f"window ({stats['dtile']},{stats['drs']}), "
-                               f"{stats['candidates']} candidates/frame, one frame per launch",
+                               f"{stats['candidates']} candidates/frame ({stats['feasible']} area-feasible), "
+                               f"one frame per launch sequence",
                    "frames": F, "width": w, "height": h, "n_threads": 8,
                    "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
-                   "sched_block": args.sched_block or 256, "sched_item": args.sched_item or 4096},
+                   "sched_block": args.sched_block or 256, "sched_item": args.sched_item or 1024,
+                   "timing": "HIP graph of one step (64 trs_partition calls), replayed K times"},
         "candidates_scored_per_s": round(fps * stats["candidates"], 1),
-        "kernel_ms": {"step1": round(avg1, 5), "step2": round(avg2, 5)},
+        "feasible_scored_per_s": round(fps * stats["feasible"], 1),
+        "eager_value": round(n_launch / eager_elapsed, 3),
+        "kernel_ms": {"features": round(avg_feat, 5), "step1": round(avg1, 5), "step2": round(avg2, 5)},
+        "step2_fraction": round(step2_frac, 4),
         "roofline": roofline,
+        "roofline_kernels": table,
         "cpu_baseline": cpu,
         "parity": parity,
     }

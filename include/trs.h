@@ -162,6 +162,17 @@ trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
                       void *workspace, size_t ws_bytes, trs_result *out_dev,
                       hipStream_t stream);
 
+/* The whole per-frame path in one call (Fig. 3 of the paper: current-frame luma and the
+ * co-located previous times in, partition out): trs_features, trs_cost_map and trs_search
+ * enqueued on one stream, with the cost map fused into the prefix-sum kernel when the CTU
+ * grid is small.  Arguments as in those three calls; feat and cost are written as they
+ * would be.  Returns as trs_search. */
+trs_status trs_partition(const trs_frame *frame, const trs_search_params *params,
+                         const uint16_t *luma, int64_t stride_elems, const uint32_t *prev,
+                         trs_blend blend, trs_feat feat, uint32_t *cost, uint32_t *flags_dev,
+                         void *workspace, size_t ws_bytes, trs_result *out_dev,
+                         hipStream_t stream);
+
 /* Host: |C| and the windows (dtile, drs) the ladder rule picks.  No device work.
  * Errors: TRS_EINVAL. */
 trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params,

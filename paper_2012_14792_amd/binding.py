@@ -91,6 +91,9 @@ def lib():
         L.trs_search.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams), P, P, P, P,
                                  ctypes.c_size_t, P, P]
         L.trs_search.restype = S
+        L.trs_partition.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams), P,
+                                    ctypes.c_int64, P, Blend, Feat, P, P, P, ctypes.c_size_t, P, P]
+        L.trs_partition.restype = S
         L.trs_space_size.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]
@@ -250,6 +253,24 @@ def trs_search(frame: Frame, params: SearchParams, cost, s1, s2, workspace, out,
     return out
 
 
+def _feat(feats: dict) -> Feat:
+    return Feat(feats["s1"].data_ptr(), feats["grad"].data_ptr(), feats["tex"].data_ptr(),
+                feats["mean"].data_ptr(), feats["var"].data_ptr(), feats["s2"].data_ptr())
+
+
+def trs_partition(frame: Frame, params: SearchParams, luma, prev, blend: Blend, feats: dict, cost,
+                  workspace, out, flags=None, stream=None):
+    """Enqueue the whole per-frame path (features -> cost map -> search) in one call."""
+    if luma.dim() != 2 or luma.element_size() != 2 or not luma.is_cuda or luma.stride(1) != 1:
+        raise TrsError(TRS_EINVAL, "trs_partition")
+    check(lib().trs_partition(ctypes.byref(frame), ctypes.byref(params), _ptr(luma), luma.stride(0),
+                              None if prev is None else _ptr(prev), blend, _feat(feats), _ptr(cost),
+                              None if flags is None else _ptr(flags), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _ptr(out),
+                              _stream(stream)), "trs_partition")
+    return out
+
+
 def read_result(out) -> dict:
     """Copy a device trs_result to the host (synchronises on it) and decode it."""
     raw = bytes(out.cpu().numpy().tobytes())
@@ -282,11 +303,20 @@ class Partitioner:
         self.out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=device)
 
     def enqueue(self, luma, prev, out=None, stream=None):
+        """Enqueue one frame (one trs_partition call); returns the device result buffer."""
+        dst = self.out if out is None else out
+        trs_partition(self.frame, self.params, luma, prev, self.blend, self.feats, self.cost,
+                      self.ws, dst, self.flags, stream)
+        return dst
+
+    def enqueue_separate(self, luma, prev, out=None, stream=None):
+        """The same path through the three separate calls."""
+        dst = self.out if out is None else out
         trs_features(self.frame, luma, self.feats, stream)
         trs_cost_map(self.frame, self.feats["tex"], prev, self.blend, self.cost, self.flags, stream)
         trs_search(self.frame, self.params, self.cost, self.feats["s1"], self.feats["s2"], self.ws,
-                   self.out if out is None else out, stream)
-        return self.out if out is None else out
+                   dst, stream)
+        return dst
 
     def __call__(self, luma, prev, stream=None) -> dict:
         self.enqueue(luma, prev, stream=stream)

@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <cstring>
 #include <array>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -23,15 +24,29 @@ struct PlanEntry {
     std::map<int, std::pair<void *, trs::SpaceView>> dev;   // per device: blob and view
 };
 
+using PlanKey = std::array<int64_t, 12>;
+
 std::mutex g_mu;
-std::map<std::vector<int64_t>, PlanEntry> g_plans;
+std::map<PlanKey, PlanEntry> g_plans;
+std::atomic<uint64_t> g_generation{1};      // bumped when plans are released
+
+// Per-thread memo of the last plan used, so repeated searches skip the lock and the map.
+struct FastPlan {
+    uint64_t generation = 0;
+    int device = -1;
+    PlanKey key{};
+    trs::SpaceView view{};
+    trs::WsLayout lay{};
+    int dt = 0, dr = 0;
+};
+thread_local FastPlan t_fast;
 
 // Timing events recorded by trs_search while profiling is on (guarded by g_prof_mu).
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<std::array<hipEvent_t, 4>> g_prof_events;
 
-std::vector<int64_t> plan_key(const trs_frame *f, const trs_search_params *p)
+PlanKey plan_key(const trs_frame *f, const trs_search_params *p)
 {
     return {f->width, f->height, f->ctu_size, p->n_threads, p->max_tile_cols, p->max_tile_rows,
             p->max_rs_per_tile, p->dtile, p->drs, p->area_k,
@@ -151,6 +166,57 @@ bool frame_ok(const trs_frame *f)
            f->bit_depth >= 8 && f->bit_depth <= 12;
 }
 
+// Validation, plan lookup (building and uploading it on first use), workspace check and
+// optional timing events for one search.
+trs_status prepare_search(const trs_frame *frame, const trs_search_params *params,
+                          void *workspace, size_t ws_bytes, trs::SearchArgs &a)
+{
+    trs_status st = trs::check_space_args(frame, params);
+    if (st != TRS_OK) return st;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256) return TRS_EWORKSPACE;
+    int dev = -1;
+    const bool have_dev = hipGetDevice(&dev) == hipSuccess;
+    const PlanKey key = plan_key(frame, params);
+    FastPlan &fp = t_fast;
+    if (!(have_dev && fp.generation == g_generation.load(std::memory_order_acquire) &&
+          fp.device == dev && fp.key == key)) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        PlanEntry *e = nullptr;
+        st = host_plan(frame, params, &e);
+        if (st != TRS_OK) return st;
+        if (ws_bytes < trs::ws_layout(*e->plan).total) return TRS_EWORKSPACE;
+        if (!have_dev) return TRS_EDEVICE;
+        trs::SpaceView v{};
+        st = device_view(*e, &v);
+        if (st != TRS_OK) return st;
+        fp.generation = g_generation.load(std::memory_order_acquire);
+        fp.device = dev;
+        fp.key = key;
+        fp.view = v;
+        fp.lay = trs::ws_layout(*e->plan);
+        fp.dt = e->plan->dt;
+        fp.dr = e->plan->dr;
+    }
+    if (ws_bytes < fp.lay.total) return TRS_EWORKSPACE;
+    a.sp = fp.view;
+    a.lay = fp.lay;
+    a.dt = fp.dt;
+    a.dr = fp.dr;
+    a.ws = static_cast<char *>(workspace);
+    a.lam_num = params->lambda_num < 0 ? -1 : params->lambda_num;
+    a.lam_den = params->lambda_den;
+    a.block = params->sched_block ? params->sched_block : 256;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof_on) {
+        std::array<hipEvent_t, 4> ev{};
+        for (auto &x : ev)
+            if (hipEventCreate(&x) != hipSuccess) return TRS_EDEVICE;
+        g_prof_events.push_back(ev);
+        for (int i = 0; i < 4; i++) a.ev[i] = ev[i];
+    }
+    return TRS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -206,42 +272,47 @@ trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
                       const uint32_t *cost, const uint32_t *s1, const uint64_t *s2,
                       void *workspace, size_t ws_bytes, trs_result *out_dev, hipStream_t stream)
 {
-    trs_status st = trs::check_space_args(frame, params);
-    if (st != TRS_OK) return st;
-    if (!cost || !s1 || !s2 || !out_dev) return TRS_EINVAL;
-    trs::SearchArgs a{};
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        PlanEntry *e = nullptr;
-        st = host_plan(frame, params, &e);
-        if (st != TRS_OK) return st;
-        a.lay = trs::ws_layout(*e->plan);
-        if (!workspace || ws_bytes < a.lay.total || reinterpret_cast<uintptr_t>(workspace) % 256)
-            return TRS_EWORKSPACE;
-        st = device_view(*e, &a.sp);
-        if (st != TRS_OK) return st;
-        a.dt = e->plan->dt;
-        a.dr = e->plan->dr;
+    if (!cost || !s1 || !s2 || !out_dev) {
+        trs_status st = trs::check_space_args(frame, params);
+        return st != TRS_OK ? st : TRS_EINVAL;
     }
+    trs::SearchArgs a{};
+    trs_status st = prepare_search(frame, params, workspace, ws_bytes, a);
+    if (st != TRS_OK) return st;
     a.cost = cost;
     a.s1 = s1;
     a.s2 = s2;
-    a.ws = static_cast<char *>(workspace);
     a.out = out_dev;
-    a.lam_num = params->lambda_num < 0 ? -1 : params->lambda_num;
-    a.lam_den = params->lambda_den;
-    a.block = params->sched_block ? params->sched_block : 256;
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (g_prof_on) {
-            std::array<hipEvent_t, 4> ev{};
-            for (auto &x : ev)
-                if (hipEventCreate(&x) != hipSuccess) return TRS_EDEVICE;
-            g_prof_events.push_back(ev);
-            for (int i = 0; i < 4; i++) a.ev[i] = ev[i];
-        }
-    }
     if (trs::launch_search(a, stream) != hipSuccess) return TRS_EDEVICE;
+    return a.sp.n_feasible == 0 ? TRS_ENOFEASIBLE : TRS_OK;
+}
+
+trs_status trs_partition(const trs_frame *frame, const trs_search_params *params,
+                         const uint16_t *luma, int64_t stride_elems, const uint32_t *prev,
+                         trs_blend blend, trs_feat feat, uint32_t *cost, uint32_t *flags_dev,
+                         void *workspace, size_t ws_bytes, trs_result *out_dev,
+                         hipStream_t stream)
+{
+    trs_status st = trs::check_space_args(frame, params);
+    if (st != TRS_OK) return st;
+    if (!luma || stride_elems < frame->width || stride_elems % 8 != 0 ||
+        reinterpret_cast<uintptr_t>(luma) % 16 != 0)
+        return TRS_EINVAL;
+    if (!feat.s1 || !feat.s2 || !feat.grad || !feat.tex || !feat.mean || !feat.var || !cost ||
+        !out_dev || blend.w_prev > 256)
+        return TRS_EINVAL;
+    trs::SearchArgs a{};
+    st = prepare_search(frame, params, workspace, ws_bytes, a);
+    if (st != TRS_OK) return st;
+    a.cost = cost;
+    a.s1 = feat.s1;
+    a.s2 = feat.s2;
+    a.out = out_dev;
+    if (trs::launch_features(frame->width, frame->height, frame->ctu_size, luma, stride_elems, feat,
+                             stream) != hipSuccess)
+        return TRS_EDEVICE;
+    if (trs::launch_partition_tail(a, feat.tex, prev, blend, cost, flags_dev, stream) != hipSuccess)
+        return TRS_EDEVICE;
     return a.sp.n_feasible == 0 ? TRS_ENOFEASIBLE : TRS_OK;
 }
 
@@ -317,6 +388,7 @@ trs_status trs_decode(const trs_frame *frame, const trs_search_params *params, i
 void trs_release_plans(void)
 {
     std::lock_guard<std::mutex> lk(g_mu);
+    g_generation.fetch_add(1, std::memory_order_acq_rel);
     for (auto &kv : g_plans)
         for (auto &d : kv.second.dev) (void)hipFree(d.second.first);
     g_plans.clear();

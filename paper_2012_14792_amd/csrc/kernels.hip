@@ -54,6 +54,9 @@ __device__ __forceinline__ long long wave_incl_scan(long long v, int lane)
 
 __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t w) { return __builtin_bit_cast(u16x2, w); }
+
 // ---------------------------------------------------------------------------------------
 // Features
 // ---------------------------------------------------------------------------------------
@@ -98,6 +101,42 @@ k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, in
 #pragma unroll
         for (int r = 0; r < R; r++)
             right[r] = (r < nrow && has_right) ? (uint32_t)row0[(long long)r * stride + 8] : 0u;
+        if (nv == 8) {
+            // Full chunk: samples stay packed two per 32-bit word.  sad_u16 adds the
+            // absolute differences of both 16-bit halves, udot2 the products of both halves.
+            uint32_t s1 = 0, s2 = 0, g = 0;
+#pragma unroll
+            for (int r = 0; r <= R; r++) {
+                if (r < nrow) {
+                    const uint32_t w0 = v[r].x, w1 = v[r].y, w2 = v[r].z, w3 = v[r].w;
+                    if (r < R) {
+                        s1 = __builtin_amdgcn_sad_u16(w0, 0u, s1);
+                        s1 = __builtin_amdgcn_sad_u16(w1, 0u, s1);
+                        s1 = __builtin_amdgcn_sad_u16(w2, 0u, s1);
+                        s1 = __builtin_amdgcn_sad_u16(w3, 0u, s1);
+                        s2 = __builtin_amdgcn_udot2(as_u16x2(w0), as_u16x2(w0), s2, false);
+                        s2 = __builtin_amdgcn_udot2(as_u16x2(w1), as_u16x2(w1), s2, false);
+                        s2 = __builtin_amdgcn_udot2(as_u16x2(w2), as_u16x2(w2), s2, false);
+                        s2 = __builtin_amdgcn_udot2(as_u16x2(w3), as_u16x2(w3), s2, false);
+                        // (p1,p2), (p3,p4), (p5,p6), (p7,right): right = p7 at the frame edge
+                        const uint32_t rw = has_right ? right[r] : (w3 >> 16);
+                        g = __builtin_amdgcn_sad_u16(__builtin_amdgcn_alignbyte(w1, w0, 2), w0, g);
+                        g = __builtin_amdgcn_sad_u16(__builtin_amdgcn_alignbyte(w2, w1, 2), w1, g);
+                        g = __builtin_amdgcn_sad_u16(__builtin_amdgcn_alignbyte(w3, w2, 2), w2, g);
+                        g = __builtin_amdgcn_sad_u16(__builtin_amdgcn_alignbyte(rw, w3, 2), w3, g);
+                    }
+                    if (r >= 1) {
+                        g = __builtin_amdgcn_sad_u16(w0, v[r - 1].x, g);
+                        g = __builtin_amdgcn_sad_u16(w1, v[r - 1].y, g);
+                        g = __builtin_amdgcn_sad_u16(w2, v[r - 1].z, g);
+                        g = __builtin_amdgcn_sad_u16(w3, v[r - 1].w, g);
+                    }
+                }
+            }
+            a1 = s1;
+            a2 = s2;
+            ag = g;
+        } else {
         uint32_t prev[8];
 #pragma unroll
         for (int r = 0; r <= R; r++) {
@@ -123,6 +162,7 @@ k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, in
 #pragma unroll
                 for (int j = 0; j < 8; j++) prev[j] = p[j];
             }
+        }
         }
     }
     unsigned long long s2 = a2;
@@ -157,14 +197,12 @@ k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, in
 // Cost map
 // ---------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256)
-k_cost(int n, const uint32_t *__restrict__ tex, const uint32_t *__restrict__ prev, uint32_t a,
-       uint32_t b, uint32_t wp, uint32_t *__restrict__ cost, uint32_t *flags)
+// Predicted time of one CTU; sets *over when the value is clamped to 2^31 - 1.
+__device__ __forceinline__ uint32_t cost_of(uint32_t tex, const uint32_t *prev, int i, uint32_t a,
+                                            uint32_t b, uint32_t wp, bool *over)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     // a + b tex <= (2^32 - 1) + (2^32 - 1)^2 < 2^64
-    const unsigned long long model = (unsigned long long)a + (unsigned long long)b * tex[i];
+    const unsigned long long model = (unsigned long long)a + (unsigned long long)b * tex;
     unsigned long long v;
     if (prev == nullptr) {
         v = model;
@@ -175,11 +213,19 @@ k_cost(int n, const uint32_t *__restrict__ tex, const uint32_t *__restrict__ pre
     } else {
         v = ((unsigned long long)wp * prev[i] + (unsigned long long)(256u - wp) * model + 128ull) >> 8;
     }
-    if (v > kCostLimit) {
-        v = kCostLimit;
-        if (flags) atomicOr(flags, 1u);
-    }
-    cost[i] = (uint32_t)v;
+    *over = v > kCostLimit;
+    return (uint32_t)(*over ? kCostLimit : v);
+}
+
+__global__ void __launch_bounds__(256)
+k_cost(int n, const uint32_t *__restrict__ tex, const uint32_t *__restrict__ prev, uint32_t a,
+       uint32_t b, uint32_t wp, uint32_t *__restrict__ cost, uint32_t *flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool over;
+    cost[i] = cost_of(tex[i], prev, i, a, b, wp, &over);
+    if (over && flags) atomicOr(flags, 1u);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -193,6 +239,7 @@ k_sat(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restric
 {
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, nw = blockDim.x / kWave;
     const int S = W + 1;
+    (void)hdr;
     for (int x = tid; x <= W; x += blockDim.x) satT[x] = satS1[x] = satS2[x] = 0;
     for (int y = wv; y < H; y += nw) {
         long long cT = 0, c1 = 0, c2 = 0;
@@ -238,62 +285,94 @@ k_sat(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restric
     }
 }
 
-// The same tables built in LDS (grids with (H+1)(W+1) <= kSatLds), written out once.
+// The same tables for grids with (H+1)(W+1) <= kSatLds: one thread per CTU row keeps
+// running sums in registers (rows are short), then one thread per column, through LDS.
 constexpr int kSatLds = 2304;
 
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(256)
 k_sat_lds(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restrict__ s1,
           const unsigned long long *__restrict__ s2, long long *satT, long long *satS1,
           long long *satS2, WsHeader *hdr)
 {
     __shared__ long long lT[kSatLds], l1[kSatLds], l2[kSatLds];
-    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, nw = blockDim.x / kWave;
-    const int S = W + 1, n = (H + 1) * S;
-    for (int e = tid; e < n; e += blockDim.x) {
-        const int y = e / S, x = e - y * S;
-        const bool in = x > 0 && y > 0;
-        const int c = (y - 1) * W + (x - 1);
-        lT[e] = in ? (long long)cost[c] : 0;
-        l1[e] = in ? (long long)s1[c] : 0;
-        l2[e] = in ? (long long)s2[c] : 0;
-    }
-    __syncthreads();
-    for (int y = 1 + wv; y <= H; y += nw) {           // rows: one wave per row
-        long long cT = 0, c1 = 0, c2 = 0;
-        for (int xb = 1; xb <= W; xb += kWave) {
-            const int x = xb + lane;
-            const int e = y * S + x;
-            long long vT = x <= W ? lT[e] : 0, v1 = x <= W ? l1[e] : 0, v2 = x <= W ? l2[e] : 0;
-            vT = wave_incl_scan(vT, lane);
-            v1 = wave_incl_scan(v1, lane);
-            v2 = wave_incl_scan(v2, lane);
-            if (x <= W) { lT[e] = vT + cT; l1[e] = v1 + c1; l2[e] = v2 + c2; }
-            cT += shfl64(vT, kWave - 1);
-            c1 += shfl64(v1, kWave - 1);
-            c2 += shfl64(v2, kWave - 1);
+    const int tid = threadIdx.x;
+    const int S = W + 1;
+    (void)hdr;
+    for (int y = tid; y < H; y += blockDim.x) {
+        long long aT = 0, a1 = 0, a2 = 0;
+        const int e0 = (y + 1) * S;
+        lT[e0] = l1[e0] = l2[e0] = 0;
+        for (int x = 0; x < W; x++) {
+            aT += cost[y * W + x];
+            a1 += s1[y * W + x];
+            a2 += (long long)s2[y * W + x];
+            lT[e0 + x + 1] = aT;
+            l1[e0 + x + 1] = a1;
+            l2[e0 + x + 1] = a2;
         }
     }
     __syncthreads();
-    for (int x = 1 + wv; x <= W; x += nw) {           // columns: one wave per column
-        long long cT = 0, c1 = 0, c2 = 0;
-        for (int yb = 1; yb <= H; yb += kWave) {
-            const int y = yb + lane;
-            const int e = y * S + x;
-            long long vT = y <= H ? lT[e] : 0, v1 = y <= H ? l1[e] : 0, v2 = y <= H ? l2[e] : 0;
-            vT = wave_incl_scan(vT, lane);
-            v1 = wave_incl_scan(v1, lane);
-            v2 = wave_incl_scan(v2, lane);
-            if (y <= H) { lT[e] = vT + cT; l1[e] = v1 + c1; l2[e] = v2 + c2; }
-            cT += shfl64(vT, kWave - 1);
-            c1 += shfl64(v1, kWave - 1);
-            c2 += shfl64(v2, kWave - 1);
+    for (int x = tid; x <= W; x += blockDim.x) {
+        long long aT = 0, a1 = 0, a2 = 0;
+        satT[x] = satS1[x] = satS2[x] = 0;
+        for (int y = 1; y <= H; y++) {
+            aT += lT[y * S + x];
+            a1 += l1[y * S + x];
+            a2 += l2[y * S + x];
+            satT[y * S + x] = aT;
+            satS1[y * S + x] = a1;
+            satS2[y * S + x] = a2;
+        }
+    }
+}
+
+// Cost map fused with the LDS prefix sums (same grids as k_sat_lds).
+__global__ void __launch_bounds__(256)
+k_cost_sat(int W, int H, const uint32_t *__restrict__ tex, const uint32_t *__restrict__ prev,
+           uint32_t a, uint32_t b, uint32_t wp, uint32_t *__restrict__ cost, uint32_t *flags,
+           const uint32_t *__restrict__ s1, const unsigned long long *__restrict__ s2,
+           long long *satT, long long *satS1, long long *satS2, WsHeader *hdr)
+{
+    __shared__ long long lT[kSatLds], l1[kSatLds], l2[kSatLds];
+    __shared__ uint32_t lc[kSatLds];
+    const int tid = threadIdx.x;
+    (void)hdr;
+    const int S = W + 1, n = W * H;
+    bool any_over = false;
+    for (int i = tid; i < n; i += blockDim.x) {
+        bool over;
+        const uint32_t v = cost_of(tex[i], prev, i, a, b, wp, &over);
+        cost[i] = v;
+        lc[i] = v;
+        any_over |= over;
+    }
+    if (any_over && flags) atomicOr(flags, 1u);
+    __syncthreads();
+    for (int y = tid; y < H; y += blockDim.x) {
+        long long aT = 0, a1 = 0, a2 = 0;
+        const int e0 = (y + 1) * S;
+        lT[e0] = l1[e0] = l2[e0] = 0;
+        for (int x = 0; x < W; x++) {
+            aT += lc[y * W + x];
+            a1 += s1[y * W + x];
+            a2 += (long long)s2[y * W + x];
+            lT[e0 + x + 1] = aT;
+            l1[e0 + x + 1] = a1;
+            l2[e0 + x + 1] = a2;
         }
     }
     __syncthreads();
-    for (int e = tid; e < n; e += blockDim.x) {
-        satT[e] = lT[e];
-        satS1[e] = l1[e];
-        satS2[e] = l2[e];
+    for (int x = tid; x <= W; x += blockDim.x) {
+        long long aT = 0, a1 = 0, a2 = 0;
+        satT[x] = satS1[x] = satS2[x] = 0;
+        for (int y = 1; y <= H; y++) {
+            aT += lT[y * S + x];
+            a1 += l1[y * S + x];
+            a2 += l2[y * S + x];
+            satT[y * S + x] = aT;
+            satS1[y * S + x] = a1;
+            satS2[y * S + x] = a2;
+        }
     }
 }
 
@@ -344,17 +423,182 @@ struct LdsMap {
     int recT, recQ, satT, satS1, satS2, bytes;
 };
 
+__device__ void score_rect(const SpaceView &sp, const long long *satT, const long long *satS1,
+                           const long long *satS2, int x0, int y0, int x1, int y1,
+                           long long *t, long long *q)
+{
+    const int S = sp.W + 1;
+    *t = rect(satT, S, x0, y0, x1, y1);
+    const unsigned area = (unsigned)(sp.colpx[x1] - sp.colpx[x0]) * (unsigned)(sp.rowpx[y1] - sp.rowpx[y0]);
+    const unsigned long long s1 = (unsigned long long)rect(satS1, S, x0, y0, x1, y1);
+    const unsigned long long s2 = (unsigned long long)rect(satS2, S, x0, y0, x1, y1);
+    *q = (long long)(s2 - floor_sq_div(s1, area));
+}
+
+// Final reduction over the step-2 partials (one per live item) and decode of the winner
+// into *out.  Run by one whole work-group of BS >= 64 threads.
+template <int BS>
+__device__ void final_block(const SpaceView &sp, const Partial *__restrict__ part, int n_part,
+                            const WsHeader *hdr, const long long *satT, const long long *satS1,
+                            const long long *satS2, trs_result *out, int dt, int dr)
+{
+    constexpr int NW = BS / kWave;
+    __shared__ unsigned long long redq[NW], redt[NW], redn[NW];
+    __shared__ long long redr[NW];
+    __shared__ int redf[NW], redi[NW];
+    __shared__ int sk[kMaxRS];                       // slices per tile of the winner
+    __shared__ long long ut[kMaxRS], uq[kMaxRS];     // uniform slice scores
+    __shared__ Key2 sbest;
+    __shared__ int sbi;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int S = sp.W + 1;
+    for (int i = tid; i <= kMaxRS; i += BS) {
+        out->col_bd[i] = 0;
+        out->row_bd[i] = 0;
+    }
+    for (int i = tid; i < kMaxRS; i += BS) {
+        for (int e = 0; e < 4; e++) out->rs[i][e] = 0;
+        out->rs_time[i] = 0;
+    }
+    for (int i = tid; i < sp.n_unif; i += BS)
+        score_rect(sp, satT, satS1, satS2, sp.unif_rs[4 * i], sp.unif_rs[4 * i + 1],
+                   sp.unif_rs[4 * i + 2], sp.unif_rs[4 * i + 3], &ut[i], &uq[i]);
+    Key2 best{kNone, kNone, LLONG_MAX, -1};
+    int bitem = -1;
+    unsigned long long scored = 0;
+    for (int i = tid; i < n_part; i += BS) {
+        const Partial p = part[i];
+        const Key2 k{p.q, p.t, p.rank, p.f};
+        scored += (unsigned long long)p.n;
+        if (p.q != kNone && key_less(k, best)) { best = k; bitem = p.item; }
+    }
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) {
+        Key2 o;
+        o.q = shfl_xor64(best.q, m);
+        o.t = shfl_xor64(best.t, m);
+        o.rank = (long long)shfl_xor64((unsigned long long)best.rank, m);
+        o.f = __shfl_xor(best.f, m, kWave);
+        const int oi = __shfl_xor(bitem, m, kWave);
+        if (key_less(o, best)) { best = o; bitem = oi; }
+        scored += shfl_xor64(scored, m);
+    }
+    if (lane == 0) {
+        redq[wv] = best.q; redt[wv] = best.t; redr[wv] = best.rank; redf[wv] = best.f;
+        redi[wv] = bitem; redn[wv] = scored;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        Key2 b{redq[0], redt[0], redr[0], redf[0]};
+        int bi = redi[0];
+        for (int i = 1; i < NW; i++) {
+            const Key2 o{redq[i], redt[i], redr[i], redf[i]};
+            if (key_less(o, b)) { b = o; bi = redi[i]; }
+        }
+        sbest = b;
+        sbi = bi;
+    }
+    __syncthreads();
+    const Key2 b = sbest;
+    const bool none = sp.n_feasible == 0 || b.q == kNone;  // uniform over the block
+    int ncols, nrows, nrs;
+    if (none) {
+        // no feasible candidate: the uniform grid
+        ncols = sp.n_unif ? sp.cu : 0;
+        nrows = sp.n_unif ? sp.ru : 0;
+        nrs = sp.n_unif;
+        for (int i = tid; i <= ncols && ncols; i += BS) out->col_bd[i] = (int)((long long)i * sp.W / sp.cu);
+        for (int i = tid; i <= nrows && nrows; i += BS) out->row_bd[i] = (int)((long long)i * sp.H / sp.ru);
+        for (int i = tid; i < nrs; i += BS) {
+            for (int e = 0; e < 4; e++) out->rs[i][e] = sp.unif_rs[4 * i + e];
+            out->rs_time[i] = ut[i];
+        }
+    } else {
+        const ItemDev it = sp.items[sbi];
+        const ShapeDev sd = sp.shapes[it.shape];
+        const int xl = b.f / it.M, m = b.f - xl * it.M;
+        const uint16_t *X = sp.xtab + sd.x_off + (long long)(it.xa + xl) * (sd.c + 1);
+        const uint16_t *Y = sp.ytab + sd.y_off + (long long)it.yi * (sd.r + 1);
+        ncols = sd.c;
+        nrows = sd.r;
+        for (int q = tid; q <= sd.c; q += BS) out->col_bd[q] = X[q];
+        for (int q = tid; q <= sd.r; q += BS) out->row_bd[q] = Y[q];
+        int opt = 0, i = 0, j = 0;
+        if (tid < sd.T) {
+            i = tid % sd.c;
+            j = tid / sd.c;
+            const int h = Y[j + 1] - Y[j];
+            opt = sp.opt_base[h] + sp.combos[it.combo_off + (long long)tid * it.M + m];
+            sk[tid] = sp.opt_k[opt];
+        }
+        __syncthreads();
+        nrs = 0;
+        for (int t = 0; t < sd.T; t++) nrs += sk[t];
+        if (tid < sd.T) {
+            int slot = 0;
+            for (int t = 0; t < tid; t++) slot += sk[t];
+            const uint16_t *z = sp.opt_z + (long long)opt * (sp.Km + 1);
+            for (int q = 0; q < sk[tid]; q++, slot++) {
+                const int y0 = Y[j] + z[q], y1 = Y[j] + z[q + 1];
+                out->rs[slot][0] = X[i];
+                out->rs[slot][1] = y0;
+                out->rs[slot][2] = X[i + 1];
+                out->rs[slot][3] = y1;
+                out->rs_time[slot] = rect(satT, S, X[i], y0, X[i + 1], y1);
+            }
+        }
+    }
+    if (tid == 0) {
+        long long tu = -1, qu = -1;
+        if (sp.n_unif > 0) {
+            tu = 0;
+            qu = 0;
+            for (int q = 0; q < sp.n_unif; q++) { tu = max(tu, ut[q]); qu += uq[q]; }
+        }
+        unsigned long long n2 = 0;
+        for (int q = 0; q < NW; q++) n2 += redn[q];
+        out->n_enumerated = sp.total;
+        out->n_feasible = sp.n_feasible;
+        out->n_step2 = (long long)n2;
+        out->dtile_used = dt;
+        out->drs_used = dr;
+        out->uniform_rank = sp.uniform_rank;
+        out->t_unif = tu;
+        out->q_unif = qu;
+        out->tile_cols = ncols;
+        out->tile_rows = nrows;
+        out->n_rs = nrs;
+        if (none) {
+            out->status = TRS_ENOFEASIBLE;
+            out->rank = sp.uniform_rank;
+            out->t_min = -1;
+            out->t_sel = tu;
+            out->q_sel = qu;
+        } else {
+            out->status = TRS_OK;
+            out->rank = b.rank;
+            out->t_min = (long long)hdr->tmin;
+            out->t_sel = (long long)b.t;
+            out->q_sel = (long long)b.q;
+        }
+    }
+}
+
 // One work item per work-group.  Phase 1 builds the item's tile-option records in LDS: for
 // a column span, tile row and (k, split offsets) option, the largest slice time (Eq. 1)
 // and, in step 2, the summed per-slice ceil-SSE (Eq. 2).  Phase 2 scores the item's
 // candidates, one per lane: T~(P) is the max of its tiles' record times, Q(P) the sum of
 // their record sums.  STAGE: the prefix sums the records read are first copied to LDS.
+//
+// Step 1 writes each item's smallest T~(P); k_live turns those into T~min, the Eq. 4
+// bound and the list of items that can hold a step-2 candidate; step 2 runs over that
+// list only; k_final reduces its partials and decodes the winner.
 template <int BS, bool P2, bool STAGE>
 __global__ void __launch_bounds__(BS)
 k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
          const long long *__restrict__ satS1, const long long *__restrict__ satS2,
-         const WsHeader *__restrict__ hdr, unsigned long long *__restrict__ item_min,
-         Partial *__restrict__ part, int lam_num, int lam_den)
+         WsHeader *hdr, unsigned long long *__restrict__ item_min, int *__restrict__ live,
+         Partial *__restrict__ part, int lam_num, int lam_den, trs_result *out, int dt, int dr)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds + L.recT);
@@ -366,6 +610,15 @@ k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
 
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int S = sp.W + 1;
+    int slot, item;
+    if (P2) {
+        const int n_live = hdr->n_live;
+        if ((int)blockIdx.x >= n_live) return;      // the item list is shorter than the grid
+        slot = xcd_item(blockIdx.x, n_live);
+        item = live[slot];
+    } else {
+        slot = item = xcd_item(blockIdx.x, gridDim.x);
+    }
     const long long *sT = satT, *s1t = satS1, *s2t = satS2;
     if (STAGE) {                       // independent of the item: overlaps its load latency
         long long *lT = reinterpret_cast<long long *>(lds + L.satT);
@@ -383,19 +636,8 @@ k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
         s1t = l1;
         s2t = l2;
     }
-    const int item = xcd_item(blockIdx.x, gridDim.x);
     const ItemDev it = sp.items[item];
-
-    unsigned long long bound = kNone;
-    if (P2) {
-        const unsigned long long tmin = hdr->tmin;
-        if (lam_num >= 0)
-            bound = tmin * (unsigned long long)(lam_den + lam_num) / (unsigned long long)lam_den;
-        if (item_min[item] > bound) {                // nothing here can pass Eq. 4
-            if (tid == 0) part[item] = Partial{kNone, kNone, LLONG_MAX, item, -1, 0, 0};
-            return;
-        }
-    }
+    const unsigned long long bound = P2 ? hdr->bound : kNone;
     if (STAGE) __syncthreads();
 
     for (int rid = tid; rid < it.n_rec; rid += BS) {
@@ -471,194 +713,62 @@ k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
                 const Key2 o{redq[i], redt[i], redr[i], redf[i]};
                 if (key_less(o, b)) b = o;
             }
-            part[item] = Partial{b.q, b.t, b.rank, item, b.f, n, 0};
+            part[slot] = Partial{b.q, b.t, b.rank, item, b.f, n, 0};
         }
     }
 }
 
-// T~min (Eq. 3): the smallest step-1 result over the work items.
+// T~min (Eq. 3) over the step-1 item minima, the Eq. 4 bound, and the list of items whose
+// minimum is within it (the only ones that can hold a step-2 candidate), in item order.
 __global__ void __launch_bounds__(1024)
-k_tmin(int n_items, const unsigned long long *__restrict__ item_min, WsHeader *hdr)
+k_live(int n_items, const unsigned long long *__restrict__ item_min, int lam_num, int lam_den,
+       WsHeader *hdr, int *__restrict__ live)
 {
-    constexpr int NW = 1024 / kWave;
+    constexpr int BS = 1024, NW = BS / kWave;
     __shared__ unsigned long long rt[NW];
+    __shared__ int wcnt[NW];
+    __shared__ int sbase;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     unsigned long long t = kNone;
-    for (int i = tid; i < n_items; i += 1024) t = min(t, item_min[i]);
+    for (int i = tid; i < n_items; i += BS) t = min(t, item_min[i]);
 #pragma unroll
     for (int m = kWave / 2; m >= 1; m >>= 1) t = min(t, shfl_xor64(t, m));
     if (lane == 0) rt[wv] = t;
+    if (tid == 0) sbase = 0;
     __syncthreads();
-    if (tid == 0) {
-        unsigned long long bt = kNone;
-        for (int i = 0; i < NW; i++) bt = min(bt, rt[i]);
-        hdr->tmin = bt;
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// Final reduction and decode
-// ---------------------------------------------------------------------------------------
-
-__device__ void score_rect(const SpaceView &sp, const long long *satT, const long long *satS1,
-                           const long long *satS2, int x0, int y0, int x1, int y1,
-                           long long *t, long long *q)
-{
-    const int S = sp.W + 1;
-    *t = rect(satT, S, x0, y0, x1, y1);
-    const unsigned area = (unsigned)(sp.colpx[x1] - sp.colpx[x0]) * (unsigned)(sp.rowpx[y1] - sp.rowpx[y0]);
-    const unsigned long long s1 = (unsigned long long)rect(satS1, S, x0, y0, x1, y1);
-    const unsigned long long s2 = (unsigned long long)rect(satS2, S, x0, y0, x1, y1);
-    *q = (long long)(s2 - floor_sq_div(s1, area));
-}
-
-__global__ void __launch_bounds__(256)
-k_final(SpaceView sp, const Partial *__restrict__ part, int n_items, const WsHeader *hdr,
-        const long long *satT, const long long *satS1, const long long *satS2,
-        trs_result *out, int dt, int dr)
-{
-    constexpr int NW = 256 / kWave;
-    __shared__ unsigned long long redq[NW], redt[NW];
-    __shared__ long long redr[NW];
-    __shared__ int redf[NW], redi[NW];
-    __shared__ int sk[kMaxRS];                       // slices per tile of the winner
-    __shared__ long long ut[kMaxRS], uq[kMaxRS];     // uniform slice scores
-    __shared__ Key2 sbest;
-    __shared__ int sbi;
-    __shared__ unsigned long long redn[NW];
-    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
-    const int S = sp.W + 1;
-    for (int i = tid; i <= kMaxRS; i += 256) {
-        out->col_bd[i] = 0;
-        out->row_bd[i] = 0;
-    }
-    for (int i = tid; i < kMaxRS; i += 256) {
-        for (int e = 0; e < 4; e++) out->rs[i][e] = 0;
-        out->rs_time[i] = 0;
-    }
-    // uniform grid scores, one slice per thread
-    if (tid < sp.n_unif)
-        score_rect(sp, satT, satS1, satS2, sp.unif_rs[4 * tid], sp.unif_rs[4 * tid + 1],
-                   sp.unif_rs[4 * tid + 2], sp.unif_rs[4 * tid + 3], &ut[tid], &uq[tid]);
-    // step-2 winner over the work items' partials
-    Key2 best{kNone, kNone, LLONG_MAX, -1};
-    int bitem = -1;
-    unsigned long long scored = 0;
-    for (int i = tid; i < n_items; i += 256) {
-        const Partial p = part[i];
-        const Key2 k{p.q, p.t, p.rank, p.f};
-        scored += (unsigned long long)p.n;
-        if (p.q != kNone && key_less(k, best)) { best = k; bitem = p.item; }
-    }
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) scored += shfl_xor64(scored, m);
-    if (lane == 0) redn[wv] = scored;
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) {
-        Key2 o;
-        o.q = shfl_xor64(best.q, m);
-        o.t = shfl_xor64(best.t, m);
-        o.rank = (long long)shfl_xor64((unsigned long long)best.rank, m);
-        o.f = __shfl_xor(best.f, m, kWave);
-        const int oi = __shfl_xor(bitem, m, kWave);
-        if (key_less(o, best)) { best = o; bitem = oi; }
-    }
-    if (lane == 0) { redq[wv] = best.q; redt[wv] = best.t; redr[wv] = best.rank; redf[wv] = best.f; redi[wv] = bitem; }
-    __syncthreads();
-    if (tid == 0) {
-        Key2 b{redq[0], redt[0], redr[0], redf[0]};
-        int bi = redi[0];
-        for (int i = 1; i < NW; i++) {
-            const Key2 o{redq[i], redt[i], redr[i], redf[i]};
-            if (key_less(o, b)) { b = o; bi = redi[i]; }
-        }
-        sbest = b;
-        sbi = bi;
-    }
-    __syncthreads();
-    const Key2 b = sbest;
-    const bool none = sp.n_feasible == 0 || b.q == kNone;  // uniform over the block
-    int ncols, nrows, nrs;
-    if (none) {
-        // no feasible candidate: the uniform grid
-        ncols = sp.n_unif ? sp.cu : 0;
-        nrows = sp.n_unif ? sp.ru : 0;
-        nrs = sp.n_unif;
-        if (tid <= ncols && ncols) out->col_bd[tid] = (int)((long long)tid * sp.W / sp.cu);
-        if (tid <= nrows && nrows) out->row_bd[tid] = (int)((long long)tid * sp.H / sp.ru);
-        if (tid < nrs) {
-            for (int e = 0; e < 4; e++) out->rs[tid][e] = sp.unif_rs[4 * tid + e];
-            out->rs_time[tid] = ut[tid];
-        }
-    } else {
-        const ItemDev it = sp.items[sbi];
-        const ShapeDev sd = sp.shapes[it.shape];
-        const int xl = b.f / it.M, m = b.f - xl * it.M;
-        const uint16_t *X = sp.xtab + sd.x_off + (long long)(it.xa + xl) * (sd.c + 1);
-        const uint16_t *Y = sp.ytab + sd.y_off + (long long)it.yi * (sd.r + 1);
-        ncols = sd.c;
-        nrows = sd.r;
-        if (tid <= sd.c) out->col_bd[tid] = X[tid];
-        if (tid <= sd.r) out->row_bd[tid] = Y[tid];
-        int opt = 0, i = 0, j = 0, h = 0;
-        if (tid < sd.T) {
-            i = tid % sd.c;
-            j = tid / sd.c;
-            h = Y[j + 1] - Y[j];
-            opt = sp.opt_base[h] + sp.combos[it.combo_off + (long long)tid * it.M + m];
-            sk[tid] = sp.opt_k[opt];
-        }
+    unsigned long long tmin = kNone;
+    for (int i = 0; i < NW; i++) tmin = min(tmin, rt[i]);
+    unsigned long long bnd = kNone;
+    if (lam_num >= 0)
+        bnd = tmin * (unsigned long long)(lam_den + lam_num) / (unsigned long long)lam_den;
+    for (int i0 = 0; i0 < n_items; i0 += BS) {
+        const int i = i0 + tid;
+        const bool keep = i < n_items && item_min[i] <= bnd;
+        const unsigned long long mask = __ballot(keep);
+        if (lane == 0) wcnt[wv] = __popcll(mask);
         __syncthreads();
-        nrs = 0;
-        for (int t = 0; t < sd.T; t++) nrs += sk[t];
-        if (tid < sd.T) {
-            int slot = 0;
-            for (int t = 0; t < tid; t++) slot += sk[t];
-            const uint16_t *z = sp.opt_z + (long long)opt * (sp.Km + 1);
-            for (int q = 0; q < sk[tid]; q++, slot++) {
-                const int y0 = Y[j] + z[q], y1 = Y[j] + z[q + 1];
-                out->rs[slot][0] = X[i];
-                out->rs[slot][1] = y0;
-                out->rs[slot][2] = X[i + 1];
-                out->rs[slot][3] = y1;
-                out->rs_time[slot] = rect(satT, S, X[i], y0, X[i + 1], y1);
-            }
-        }
+        int off = sbase;
+        for (int q = 0; q < wv; q++) off += wcnt[q];
+        if (keep) live[off + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+        __syncthreads();
+        if (tid == 0) for (int q = 0; q < NW; q++) sbase += wcnt[q];
+        __syncthreads();
     }
     if (tid == 0) {
-        long long tu = -1, qu = -1;
-        if (sp.n_unif > 0) {
-            tu = 0;
-            qu = 0;
-            for (int q = 0; q < sp.n_unif; q++) { tu = max(tu, ut[q]); qu += uq[q]; }
-        }
-        out->n_enumerated = sp.total;
-        out->n_feasible = sp.n_feasible;
-        unsigned long long n2 = 0;
-        for (int q = 0; q < NW; q++) n2 += redn[q];
-        out->n_step2 = (long long)n2;
-        out->dtile_used = dt;
-        out->drs_used = dr;
-        out->uniform_rank = sp.uniform_rank;
-        out->t_unif = tu;
-        out->q_unif = qu;
-        out->tile_cols = ncols;
-        out->tile_rows = nrows;
-        out->n_rs = nrs;
-        if (none) {
-            out->status = TRS_ENOFEASIBLE;
-            out->rank = sp.uniform_rank;
-            out->t_min = -1;
-            out->t_sel = tu;
-            out->q_sel = qu;
-        } else {
-            out->status = TRS_OK;
-            out->rank = b.rank;
-            out->t_min = (long long)hdr->tmin;
-            out->t_sel = (long long)b.t;
-            out->q_sel = (long long)b.q;
-        }
+        hdr->tmin = tmin;
+        hdr->bound = bnd;
+        hdr->n_live = sbase;
     }
+}
+
+// Winner over the step-2 partials of the live items (none for a plan without any
+// area-feasible candidate), decoded into *out.
+__global__ void __launch_bounds__(256)
+k_final(SpaceView sp, const Partial *__restrict__ part, const WsHeader *hdr,
+        const long long *satT, const long long *satS1, const long long *satS2, trs_result *out,
+        int dt, int dr)
+{
+    final_block<256>(sp, part, sp.n_items ? hdr->n_live : 0, hdr, satT, satS1, satS2, out, dt, dr);
 }
 
 // LDS layout of a search kernel: records and (when staged) the prefix sums.
@@ -684,37 +794,70 @@ LdsMap lds_map(const SpaceView &sp, bool p2, bool stage)
 
 constexpr int kStageLimit = 24 * 1024;   // prefix sums copied to LDS only up to this size
 
+struct WsPtrs {
+    WsHeader *hdr;
+    long long *satT, *satS1, *satS2;
+    unsigned long long *imin;
+    int *live;
+    Partial *part;
+};
+
+WsPtrs ws_ptrs(const SearchArgs &a)
+{
+    return WsPtrs{reinterpret_cast<WsHeader *>(a.ws + a.lay.header),
+                  reinterpret_cast<long long *>(a.ws + a.lay.satT),
+                  reinterpret_cast<long long *>(a.ws + a.lay.satS1),
+                  reinterpret_cast<long long *>(a.ws + a.lay.satS2),
+                  reinterpret_cast<unsigned long long *>(a.ws + a.lay.item_min),
+                  reinterpret_cast<int *>(a.ws + a.lay.live),
+                  reinterpret_cast<Partial *>(a.ws + a.lay.partial)};
+}
+
 template <int BS, bool P2>
-void launch_pass(const SearchArgs &a, const long long *satT, const long long *satS1,
-                 const long long *satS2, WsHeader *hdr, unsigned long long *imin, Partial *part,
-                 hipStream_t s)
+void launch_pass(const SearchArgs &a, const WsPtrs &w, hipStream_t s)
 {
     const int G = a.sp.n_items;
     const int satb = 8 * (a.sp.W + 1) * (a.sp.H + 1) * (P2 ? 3 : 1);
     if (satb <= kStageLimit) {
         const LdsMap L = lds_map(a.sp, P2, true);
-        hipLaunchKernelGGL((k_search<BS, P2, true>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, satT,
-                           satS1, satS2, hdr, imin, part, a.lam_num, a.lam_den);
+        hipLaunchKernelGGL((k_search<BS, P2, true>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, w.satT,
+                           w.satS1, w.satS2, w.hdr, w.imin, w.live, w.part, a.lam_num, a.lam_den,
+                           a.out, a.dt, a.dr);
     } else {
         const LdsMap L = lds_map(a.sp, P2, false);
-        hipLaunchKernelGGL((k_search<BS, P2, false>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, satT,
-                           satS1, satS2, hdr, imin, part, a.lam_num, a.lam_den);
+        hipLaunchKernelGGL((k_search<BS, P2, false>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, w.satT,
+                           w.satS1, w.satS2, w.hdr, w.imin, w.live, w.part, a.lam_num, a.lam_den,
+                           a.out, a.dt, a.dr);
     }
 }
 
 template <int BS>
-hipError_t launch_passes(const SearchArgs &a, long long *satT, long long *satS1, long long *satS2,
-                         WsHeader *hdr, unsigned long long *imin, Partial *part, hipStream_t s)
+hipError_t launch_passes(const SearchArgs &a, const WsPtrs &w, hipStream_t s)
 {
-    const bool any = a.sp.n_items > 0;
-    if (a.ev[0] && hipEventRecord(a.ev[0], s) != hipSuccess) return hipErrorUnknown;
-    if (any) launch_pass<BS, false>(a, satT, satS1, satS2, hdr, imin, part, s);
-    if (a.ev[1] && hipEventRecord(a.ev[1], s) != hipSuccess) return hipErrorUnknown;
-    if (any) hipLaunchKernelGGL(k_tmin, dim3(1), dim3(1024), 0, s, a.sp.n_items, imin, hdr);
-    if (a.ev[2] && hipEventRecord(a.ev[2], s) != hipSuccess) return hipErrorUnknown;
-    if (any) launch_pass<BS, true>(a, satT, satS1, satS2, hdr, imin, part, s);
-    if (a.ev[3] && hipEventRecord(a.ev[3], s) != hipSuccess) return hipErrorUnknown;
+    if (a.sp.n_items > 0) {
+        if (a.ev[0] && hipEventRecord(a.ev[0], s) != hipSuccess) return hipErrorUnknown;
+        launch_pass<BS, false>(a, w, s);
+        if (a.ev[1] && hipEventRecord(a.ev[1], s) != hipSuccess) return hipErrorUnknown;
+        hipLaunchKernelGGL(k_live, dim3(1), dim3(1024), 0, s, a.sp.n_items, w.imin, a.lam_num,
+                           a.lam_den, w.hdr, w.live);
+        if (a.ev[2] && hipEventRecord(a.ev[2], s) != hipSuccess) return hipErrorUnknown;
+        launch_pass<BS, true>(a, w, s);
+        if (a.ev[3] && hipEventRecord(a.ev[3], s) != hipSuccess) return hipErrorUnknown;
+    }
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, a.sp, w.part, w.hdr, w.satT, w.satS1,
+                       w.satS2, a.out, a.dt, a.dr);
     return hipGetLastError();
+}
+
+hipError_t launch_after_sat(const SearchArgs &a, hipStream_t s)
+{
+    const WsPtrs w = ws_ptrs(a);
+    switch (a.block) {
+    case 64: return launch_passes<64>(a, w, s);
+    case 128: return launch_passes<128>(a, w, s);
+    case 512: return launch_passes<512>(a, w, s);
+    default: return launch_passes<256>(a, w, s);
+    }
 }
 
 }  // namespace
@@ -724,13 +867,15 @@ WsLayout ws_layout(const Plan &pl)
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
     WsLayout l{};
     const size_t sat = sizeof(long long) * (size_t)(pl.W + 1) * (pl.H + 1);
+    const size_t n = pl.items.size();
     l.header = 0;
     l.satT = up(sizeof(WsHeader));
     l.satS1 = l.satT + up(sat);
     l.satS2 = l.satS1 + up(sat);
     l.item_min = l.satS2 + up(sat);
-    l.partial = l.item_min + up(sizeof(unsigned long long) * pl.items.size());
-    l.total = l.partial + up(sizeof(Partial) * pl.items.size());
+    l.live = l.item_min + up(sizeof(unsigned long long) * n);
+    l.partial = l.live + up(sizeof(int) * n);
+    l.total = l.partial + up(sizeof(Partial) * n);
     return l;
 }
 
@@ -766,29 +911,30 @@ hipError_t launch_cost_map(int n, const uint32_t *tex, const uint32_t *prev, trs
 
 hipError_t launch_search(const SearchArgs &a, hipStream_t s)
 {
-    auto *hdr = reinterpret_cast<WsHeader *>(a.ws + a.lay.header);
-    auto *satT = reinterpret_cast<long long *>(a.ws + a.lay.satT);
-    auto *satS1 = reinterpret_cast<long long *>(a.ws + a.lay.satS1);
-    auto *satS2 = reinterpret_cast<long long *>(a.ws + a.lay.satS2);
-    auto *imin = reinterpret_cast<unsigned long long *>(a.ws + a.lay.item_min);
-    auto *part = reinterpret_cast<Partial *>(a.ws + a.lay.partial);
+    const WsPtrs w = ws_ptrs(a);
     if ((a.sp.W + 1) * (a.sp.H + 1) <= kSatLds)
-        hipLaunchKernelGGL(k_sat_lds, dim3(1), dim3(512), 0, s, a.sp.W, a.sp.H, a.cost, a.s1,
-                           (const unsigned long long *)a.s2, satT, satS1, satS2, hdr);
+        hipLaunchKernelGGL(k_sat_lds, dim3(1), dim3(256), 0, s, a.sp.W, a.sp.H, a.cost, a.s1,
+                           (const unsigned long long *)a.s2, w.satT, w.satS1, w.satS2, w.hdr);
     else
         hipLaunchKernelGGL(k_sat, dim3(1), dim3(256), 0, s, a.sp.W, a.sp.H, a.cost, a.s1,
-                           (const unsigned long long *)a.s2, satT, satS1, satS2, hdr);
-    hipError_t e;
-    switch (a.block) {
-    case 64: e = launch_passes<64>(a, satT, satS1, satS2, hdr, imin, part, s); break;
-    case 128: e = launch_passes<128>(a, satT, satS1, satS2, hdr, imin, part, s); break;
-    case 512: e = launch_passes<512>(a, satT, satS1, satS2, hdr, imin, part, s); break;
-    default: e = launch_passes<256>(a, satT, satS1, satS2, hdr, imin, part, s); break;
+                           (const unsigned long long *)a.s2, w.satT, w.satS1, w.satS2, w.hdr);
+    return launch_after_sat(a, s);
+}
+
+hipError_t launch_partition_tail(const SearchArgs &a, const uint32_t *tex, const uint32_t *prev,
+                                 trs_blend b, uint32_t *cost, uint32_t *flags, hipStream_t s)
+{
+    const WsPtrs w = ws_ptrs(a);
+    if ((a.sp.W + 1) * (a.sp.H + 1) <= kSatLds) {
+        hipLaunchKernelGGL(k_cost_sat, dim3(1), dim3(256), 0, s, a.sp.W, a.sp.H, tex, prev, b.a,
+                           b.b, b.w_prev, cost, flags, a.s1, (const unsigned long long *)a.s2,
+                           w.satT, w.satS1, w.satS2, w.hdr);
+        if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
+        return launch_after_sat(a, s);
     }
+    const hipError_t e = launch_cost_map(a.sp.W * a.sp.H, tex, prev, b, cost, flags, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, a.sp, part, a.sp.n_items, hdr, satT,
-                       satS1, satS2, a.out, a.dt, a.dr);
-    return hipGetLastError();
+    return launch_search(a, s);
 }
 
 }  // namespace trs

@@ -211,3 +211,59 @@ def test_repeated_runs_are_bit_identical(orc):
         outs.append(out)
     torch.cuda.synchronize()
     assert all(torch.equal(outs[0], o) for o in outs[1:])
+
+
+def test_separate_calls_match_fused_call(orc):
+    import torch
+    cfg = synth.CONFIGS["uhd_n8"]
+    w, h = cfg["width"], cfg["height"]
+    p = B.make_params(8, 6, 4, 4, lam=cfg["lam"])
+    part = B.Partitioner(w, h, p)
+    (f, luma, prev), = list(sequence_inputs(orc, cfg, [9]))
+    d = to_device(luma)
+    pv = torch.from_numpy(prev.view(np.int32)).cuda()
+    a = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    b = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    part.enqueue(d, pv, out=a)
+    part.enqueue_separate(d, pv, out=b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert_same_result(B.read_result(a), orc.partition(luma, prev, oracle_params(orc, p)), "fused")
+
+
+def test_graph_replay_matches_eager(orc):
+    """Every replay of a captured multi-frame graph equals the eager results."""
+    import torch
+    cfg = synth.CONFIGS["uhd_n8"]
+    w, h = cfg["width"], cfg["height"]
+    p = B.make_params(8, 6, 4, 4, lam=cfg["lam"])
+    part = B.Partitioner(w, h, p)
+    frames = list(sequence_inputs(orc, cfg, [3, 4, 5, 6]))
+    lumas = [to_device(l) for _, l, _ in frames]
+    prevs = [torch.from_numpy(pv.view(np.int32)).cuda() for _, _, pv in frames]
+    eager = torch.empty((len(frames), B.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+    for i in range(len(frames)):
+        part.enqueue(lumas[i], prevs[i], out=eager[i])
+    torch.cuda.synchronize()
+    graphed = torch.zeros_like(eager)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for i in range(len(frames)):
+                part.enqueue(lumas[i], prevs[i], out=graphed[i])
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graphed.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(graphed, eager), f"replay {rep}"
+        # eager work between replays reuses the same workspace
+        part.enqueue(lumas[0], prevs[0], out=eager[0])
+        torch.cuda.synchronize()
+    for i, (f, luma, prev) in enumerate(frames):
+        assert_same_result(B.read_result(graphed[i]), orc.partition(luma, prev, oracle_params(orc, p)),
+                           f"graph frame {f}")
