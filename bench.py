@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=16, help="oracle worker threads (cap)")
     ap.add_argument("--sched-block", type=int, default=0)
     ap.add_argument("--sched-item", type=int, default=0)
+    ap.add_argument("--streams", type=int, default=8, help="frames in flight (one stream each)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 1 GiB once before timing (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -102,12 +103,24 @@ def main():
         del src, dst
         log("copy probe: 1 GiB device-to-device copy done")
 
-    part = B.Partitioner(w, h, params)
+    # frames are independent: S streams (default priority) each run whole frames, so the
+    # kernels of up to S frames overlap; each stream owns its buffers and workspace
+    S = max(1, args.streams)
+    parts = [B.Partitioner(w, h, params) for _ in range(S)]
+    part = parts[0]
     outs = torch.empty((F, B.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+    streams = [torch.cuda.Stream() for _ in range(S)]
 
     def step():
+        base = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(base)
         for f in range(F):
-            part.enqueue(luma[f], prev[f], out=outs[f])
+            k = f % S
+            with torch.cuda.stream(streams[k]):
+                parts[k].enqueue(luma[f], prev[f], out=outs[f])
+        for st in streams:
+            base.wait_stream(st)
 
     # warm up eagerly (builds and uploads the plan), then capture one step in a HIP graph
     for _ in range(max(args.warmup, 1)):
@@ -123,7 +136,7 @@ def main():
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps), step captured as a graph of {F} frames")
+    log(f"warmup done ({args.warmup} steps), step captured as a graph of {F} frames on {S} streams")
 
     # ---- timed region: K graph replays, one per step ---------------------------------------
     torch.cuda.synchronize()
@@ -134,6 +147,7 @@ def main():
     elapsed = time.perf_counter() - t_start
     fps = F * args.steps / elapsed
     log(f"timed {args.steps} graph replays in {elapsed:.3f} s: {fps:.1f} frames/s")
+    graph_outs = outs.clone()
 
     # ---- eager steps with HIP events around each kernel of interest ------------------------
     # (events on the stream the kernels run on: torch's current stream)
@@ -155,7 +169,8 @@ def main():
     ms1, ms2, n_search = B.trs_profile_read()
     n_launch = F * args.steps
     avg_feat, avg1, avg2 = feat_ms / n_launch, ms1 / max(n_search, 1), ms2 / max(n_search, 1)
-    res_all = [B.result_dict(B.Result.from_buffer_copy(bytes(outs[f].cpu().numpy().tobytes())))
+    eager_equals_graph = bool(torch.equal(outs, graph_outs))
+    res_all = [B.result_dict(B.Result.from_buffer_copy(bytes(graph_outs[f].cpu().numpy().tobytes())))
                for f in range(F)]
     step2_frac = sum(r["n_step2"] for r in res_all) / max(1, sum(r["n_feasible"] for r in res_all))
     log(f"eager: {n_launch / eager_elapsed:.1f} frames/s; kernel ms features {avg_feat:.4f} "
@@ -196,29 +211,28 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         cores = min(len(os.sched_getaffinity(0)), args.cpu_threads)
-        S = min(F, args.cpu_frames or 2 * cores)
+        n_cpu = min(F, args.cpu_frames or 2 * cores)
         oparams = oracle.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
                                      cfg["max_rs_per_tile"], lam=cfg["lam"])
-        otex = [oracle.features(frames[f])["tex"] for f in range(S)]
-        oprev = [synth.ctu_times(otex[max(f - 1, 0)], eps[max(f - 1, 0)]) for f in range(S)]
-        log(f"cpu baseline: oracle on {S} frames with {cores} threads")
+        otex = [oracle.features(frames[f])["tex"] for f in range(n_cpu)]
+        oprev = [synth.ctu_times(otex[max(f - 1, 0)], eps[max(f - 1, 0)]) for f in range(n_cpu)]
+        log(f"cpu baseline: oracle on {n_cpu} frames with {cores} threads")
         t0 = time.perf_counter()
         with cf.ThreadPoolExecutor(cores) as ex:
-            refs = list(ex.map(lambda f: oracle.partition(frames[f], oprev[f], oparams), range(S)))
+            refs = list(ex.map(lambda f: oracle.partition(frames[f], oprev[f], oparams), range(n_cpu)))
         wall = time.perf_counter() - t0
-        cpu = {"value": round(S / wall, 4), "unit": "4K frames/s", "cores": cores, "kind": "oracle",
-               "sample": f"frames 0..{S - 1} of the same 64-frame 4K sequence, whole path "
+        cpu = {"value": round(n_cpu / wall, 4), "unit": "4K frames/s", "cores": cores, "kind": "oracle",
+               "sample": f"frames 0..{n_cpu - 1} of the same 64-frame 4K sequence, whole path "
                          f"(features, time map, two-step search), one frame per thread, "
                          f"{wall:.1f} s wall"}
-        host = B.Result
         ok = 0
-        for f in range(S):
-            g = B.result_dict(host.from_buffer_copy(bytes(outs[f].cpu().numpy().tobytes())))
+        for f in range(n_cpu):
+            g = res_all[f]
             r = refs[f]
             same = all(g[k] == r[k] for k in ("rank", "t_min", "t_sel", "q_sel", "n_feasible", "rs_time")) \
                 and [tuple(x) for x in g["rs"]] == [tuple(x) for x in r["rs"]]
             ok += same
-        parity = f"{ok}/{S} frames bit-exact vs oracle"
+        parity = f"{ok}/{n_cpu} graph-replayed frames bit-exact vs oracle; eager == graph: {eager_equals_graph}"
         log(parity)
 
     res = {
@@ -241,8 +255,9 @@ def main():
                                f"one frame per launch sequence",
                    "frames": F, "width": w, "height": h, "n_threads": 8,
                    "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
-                   "sched_block": args.sched_block or 256, "sched_item": args.sched_item or 1024,
-                   "timing": "HIP graph of one step (64 trs_partition calls), replayed K times"},
+                   "sched_block": args.sched_block or 256, "sched_item": args.sched_item or 512,
+                   "streams": S,
+                   "timing": f"HIP graph of one step ({F} trs_partition calls over {S} streams), replayed K times"},
         "candidates_scored_per_s": round(fps * stats["candidates"], 1),
         "feasible_scored_per_s": round(fps * stats["feasible"], 1),
         "eager_value": round(n_launch / eager_elapsed, 3),

@@ -90,7 +90,7 @@ typedef struct trs_blend {
  *                   holds at most space_budget candidates (else (0,0));
  *   space_budget    ladder budget, <= 0 means 2^24;
  *   sched_block     work-group size for the search kernels (64, 128, 256, 512; 0 = 256);
- *   sched_item      target candidates per work item (0 = library default).  The schedule
+ *   sched_item      target area-feasible candidates per work item (0 = 512).  The schedule
  *                   changes speed only, never the result. */
 typedef struct trs_search_params {
     int32_t n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile;

@@ -276,7 +276,7 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
 
     // Combination tables per (shape, Y), in canonical order.
     int64_t rank_base = 0;
-    const int64_t target = p->sched_item > 0 ? p->sched_item : 1024;
+    const int64_t target = p->sched_item > 0 ? p->sched_item : 512;
     for (auto &s : sh) {
         const int c = s.c, r = s.r, T = c * r;
         const int kcap = std::min(Km, N - (T - 1));
