@@ -173,6 +173,49 @@ trs_status trs_partition(const trs_frame *frame, const trs_search_params *params
                          void *workspace, size_t ws_bytes, trs_result *out_dev,
                          hipStream_t stream);
 
+/* ---- Batched form: many frames, each with its own geometry and parameters ----
+ * One description per frame: geometry, search parameters, its luma (device, layout as in
+ * trs_features), its previous-frame CTU times (device, nullable) and blend. */
+typedef struct trs_batch_frame {
+    trs_frame frame;
+    trs_search_params params;
+    const uint16_t *luma;
+    int64_t stride_elems;
+    const uint32_t *prev;
+    trs_blend blend;
+} trs_batch_frame;
+
+typedef struct trs_batch_s *trs_batch;
+
+/* Host: build (or reuse) each frame's candidate-space plan and upload the batch's frame
+ * descriptors and work list to the current device (allocates; synchronous).  The luma and
+ * prev pointers are recorded: trs_batch_run reads them as they are when it runs.  All frames
+ * share one ctu_size, and each frame's CTU grid must satisfy (W + 1) (H + 1) <= 2304.
+ * block: work-group size of the search kernels (0 = 256); wgs_per_cu: resident work-groups
+ * per CU of the persistent search kernels (0 = as many as fit).
+ * Errors: TRS_EINVAL, TRS_ENOSPACE, TRS_ENOTIMPL (grid too large), TRS_EDEVICE. */
+trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int32_t block,
+                            int32_t wgs_per_cu, trs_batch *out);
+
+/* Host: workspace bytes trs_batch_run needs (256-byte aligned device memory). */
+trs_status trs_batch_workspace(trs_batch batch, size_t *bytes);
+
+/* The whole path for every frame of the batch (per-CTU features, time maps, prefix sums,
+ * both search steps, decode), enqueued on `stream` as six launches for the whole batch, with
+ * the two search steps as persistent kernels over all frames' work items.  Frame f's result
+ * (as trs_search's) goes to out_dev[f].  Capturable in a HIP graph.
+ * Errors: TRS_EINVAL, TRS_EWORKSPACE, TRS_EDEVICE. */
+trs_status trs_batch_run(trs_batch batch, void *workspace, size_t ws_bytes, trs_result *out_dev,
+                         hipStream_t stream);
+
+/* Host: device pointers of frame `frame`'s per-CTU features and time map inside a batch
+ * workspace (valid after trs_batch_run on that workspace).  Errors: TRS_EINVAL. */
+trs_status trs_batch_frame_arrays(trs_batch batch, void *workspace, int32_t frame,
+                                  trs_feat *feat, uint32_t **cost);
+
+/* Host: free the batch's device tables (plans stay cached). */
+void trs_batch_destroy(trs_batch batch);
+
 /* Host: |C| and the windows (dtile, drs) the ladder rule picks.  No device work.
  * Errors: TRS_EINVAL. */
 trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params,
@@ -208,7 +251,8 @@ trs_status trs_decode(const trs_frame *frame, const trs_search_params *params, i
 void trs_profile_enable(int on);
 trs_status trs_profile_read(double *ms_step1, double *ms_step2, int64_t *searches);
 
-/* Host: drop every cached candidate-space plan and free its device tables. */
+/* Host: drop every cached candidate-space plan and free its device tables.  Batches created
+ * before this call must be destroyed, not run, afterwards. */
 void trs_release_plans(void);
 
 /* Static description of a status code. */

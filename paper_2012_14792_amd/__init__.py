@@ -5,7 +5,7 @@ two-step search) runs in the HIP kernels of libtrs.so; ``binding`` marshals argu
 its C ABI (include/trs.h).
 """
 from . import binding  # noqa: F401
-from .binding import (Partitioner, TrsError, make_frame, make_params, read_result,  # noqa: F401
+from .binding import (Batch, Partitioner, TrsError, make_frame, make_params, read_result,  # noqa: F401
                       trs_partition,
                       trs_search_stats, trs_profile_enable, trs_profile_read,
                       trs_cost_map, trs_decode, trs_features, trs_release_plans, trs_search,

@@ -63,6 +63,11 @@ class Result(ctypes.Structure):
                 ("rs", (ctypes.c_int32 * 4) * MAX_RS), ("rs_time", ctypes.c_int64 * MAX_RS)]
 
 
+class BatchFrame(ctypes.Structure):
+    _fields_ = [("frame", Frame), ("params", SearchParams), ("luma", ctypes.c_void_p),
+                ("stride_elems", ctypes.c_int64), ("prev", ctypes.c_void_p), ("blend", Blend)]
+
+
 RESULT_BYTES = ctypes.sizeof(Result)
 _lib = None
 
@@ -111,6 +116,18 @@ def lib():
         L.trs_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
         L.trs_profile_read.restype = S
+        L.trs_batch_create.argtypes = [ctypes.POINTER(BatchFrame), ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+        L.trs_batch_create.restype = S
+        L.trs_batch_workspace.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        L.trs_batch_workspace.restype = S
+        L.trs_batch_run.argtypes = [P, P, ctypes.c_size_t, P, P]
+        L.trs_batch_run.restype = S
+        L.trs_batch_frame_arrays.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(Feat),
+                                             ctypes.POINTER(ctypes.c_void_p)]
+        L.trs_batch_frame_arrays.restype = S
+        L.trs_batch_destroy.argtypes = [P]
+        L.trs_batch_destroy.restype = None
         L.trs_strerror.argtypes = [S]
         L.trs_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -321,3 +338,77 @@ class Partitioner:
     def __call__(self, luma, prev, stream=None) -> dict:
         self.enqueue(luma, prev, stream=stream)
         return read_result(self.out)
+
+
+class Batch:
+    """The batched form: every frame of a list through the whole path in six launches.
+
+    frames: list of dicts with keys width, height, params (SearchParams), luma (2-D CUDA
+    uint16/int16 tensor), prev (CUDA int32 tensor or None) and optional blend (a, b, w_prev),
+    ctu_size.  The tensors must stay alive and in place while the batch is used.
+    """
+
+    def __init__(self, frames, block: int = 0, wgs_per_cu: int = 0, device="cuda"):
+        import torch
+        self._keep = []
+        arr = (BatchFrame * len(frames))()
+        for i, fr in enumerate(frames):
+            luma = fr["luma"]
+            if luma.dim() != 2 or luma.element_size() != 2 or not luma.is_cuda or luma.stride(1) != 1:
+                raise TrsError(TRS_EINVAL, "Batch")
+            prev = fr.get("prev")
+            arr[i].frame = make_frame(fr["width"], fr["height"], fr.get("ctu_size", 128), 10)
+            arr[i].params = fr["params"]
+            arr[i].luma = luma.data_ptr()
+            arr[i].stride_elems = luma.stride(0)
+            arr[i].prev = None if prev is None else prev.data_ptr()
+            arr[i].blend = Blend(*fr.get("blend", (200, 3, 256)))
+            self._keep += [luma, prev]
+        h = ctypes.c_void_p()
+        check(lib().trs_batch_create(arr, len(frames), block, wgs_per_cu, ctypes.byref(h)), "trs_batch_create")
+        self._h = h
+        self.n = len(frames)
+        nb = ctypes.c_size_t()
+        check(lib().trs_batch_workspace(h, ctypes.byref(nb)), "trs_batch_workspace")
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        self.out = torch.empty((self.n, RESULT_BYTES), dtype=torch.uint8, device=device)
+
+    def enqueue(self, stream=None):
+        check(lib().trs_batch_run(self._h, _ptr(self.ws), self.ws.numel(), _ptr(self.out), _stream(stream)),
+              "trs_batch_run")
+        return self.out
+
+    def results(self) -> list:
+        raw = self.out.cpu().numpy()
+        return [result_dict(Result.from_buffer_copy(bytes(raw[i].tobytes()))) for i in range(self.n)]
+
+    def frame_arrays(self, i: int) -> tuple[Feat, int]:
+        feat, cost = Feat(), ctypes.c_void_p()
+        check(lib().trs_batch_frame_arrays(self._h, _ptr(self.ws), i, ctypes.byref(feat), ctypes.byref(cost)),
+              "trs_batch_frame_arrays")
+        return feat, cost.value
+
+    def capture(self):
+        """A CUDA/HIP graph whose replay runs the whole batch."""
+        import torch
+        self.enqueue()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.enqueue()
+        torch.cuda.current_stream().wait_stream(s)
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().trs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

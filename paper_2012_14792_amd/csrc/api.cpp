@@ -219,6 +219,14 @@ trs_status prepare_search(const trs_frame *frame, const trs_search_params *param
 
 }  // namespace
 
+struct trs_batch_s {
+    int device = -1;
+    trs::BatchLaunch launch{};
+    size_t ws_bytes = 0;
+    void *blob = nullptr;
+    std::vector<trs::BatchFrameDev> frames;
+};
+
 extern "C" {
 
 trs_status trs_features(const trs_frame *frame, const uint16_t *luma, int64_t stride_elems,
@@ -383,6 +391,161 @@ trs_status trs_decode(const trs_frame *frame, const trs_search_params *params, i
     if (st != TRS_OK) return st;
     std::memset(out_host, 0, sizeof(*out_host));
     return trs::decode_rank(*e->plan, rank, out_host);
+}
+
+trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int32_t block,
+                            int32_t wgs_per_cu, trs_batch *out)
+{
+    if (!frames || n_frames < 1 || !out || wgs_per_cu < 0) return TRS_EINVAL;
+    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return TRS_EINVAL;
+    const int cs = frames[0].frame.ctu_size;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TRS_EDEVICE;
+    auto b = std::make_unique<trs_batch_s>();
+    b->device = dev;
+    std::vector<trs::SpaceView> views;
+    std::vector<const PlanEntry *> plan_of_view;
+    std::vector<int> ctu_frame, item_frame;
+    long long off = 0;
+    int rec_max = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int f = 0; f < n_frames; f++) {
+            const trs_batch_frame &bf = frames[f];
+            trs_status st = trs::check_space_args(&bf.frame, &bf.params);
+            if (st != TRS_OK) return st;
+            if (bf.frame.ctu_size != cs || !bf.luma || bf.stride_elems < bf.frame.width ||
+                bf.stride_elems % 8 != 0 || reinterpret_cast<uintptr_t>(bf.luma) % 16 != 0 ||
+                bf.blend.w_prev > 256)
+                return TRS_EINVAL;
+            const int W = (bf.frame.width + cs - 1) / cs, H = (bf.frame.height + cs - 1) / cs;
+            if ((W + 1) * (H + 1) > 2304) return TRS_ENOTIMPL;
+            PlanEntry *e = nullptr;
+            st = host_plan(&bf.frame, &bf.params, &e);
+            if (st != TRS_OK) return st;
+            trs::SpaceView v{};
+            st = device_view(*e, &v);
+            if (st != TRS_OK) return st;
+            int pi = -1;
+            for (size_t q = 0; q < plan_of_view.size(); q++)
+                if (plan_of_view[q] == e) pi = (int)q;
+            if (pi < 0) {
+                pi = (int)views.size();
+                views.push_back(v);
+                plan_of_view.push_back(e);
+            }
+            rec_max = std::max(rec_max, v.rec_max);
+            trs::BatchFrameDev fd{};
+            fd.luma = bf.luma;
+            fd.stride = bf.stride_elems;
+            fd.prev = bf.prev;
+            fd.a = bf.blend.a;
+            fd.b = bf.blend.b;
+            fd.wp = bf.blend.w_prev;
+            fd.w = bf.frame.width;
+            fd.h = bf.frame.height;
+            fd.W = W;
+            fd.H = H;
+            fd.plan = pi;
+            fd.lam_num = bf.params.lambda_num < 0 ? -1 : bf.params.lambda_num;
+            fd.lam_den = bf.params.lambda_den;
+            fd.dt = e->plan->dt;
+            fd.dr = e->plan->dr;
+            fd.ctu_base = (int)ctu_frame.size();
+            fd.item_base = (int)item_frame.size();
+            fd.n_items = (int)e->plan->items.size();
+            off = trs::batch_frame_region(W, H, &fd, off);
+            ctu_frame.insert(ctu_frame.end(), (size_t)W * H, f);
+            item_frame.insert(item_frame.end(), (size_t)fd.n_items, f);
+            if (item_frame.size() > (size_t)INT32_MAX / 2) return TRS_ENOSPACE;
+            b->frames.push_back(fd);
+        }
+    }
+    const long long total_items = (long long)item_frame.size();
+    auto up = [](long long v) { return (v + 255) & ~255ll; };
+    b->launch.o_item_min = up(off);
+    b->launch.o_part = b->launch.o_item_min + up(8 * total_items);
+    b->ws_bytes = (size_t)(b->launch.o_part + up((long long)sizeof(trs::Partial) * total_items));
+    // device copy of views, frames and the two index lists
+    std::vector<std::tuple<const void *, size_t, size_t>> parts;
+    size_t boff = 0;
+    size_t o_views = add_array(parts, boff, views);
+    size_t o_frames = add_array(parts, boff, b->frames);
+    size_t o_cf = add_array(parts, boff, ctu_frame);
+    size_t o_if = add_array(parts, boff, item_frame);
+    const size_t bytes = (boff + 255) & ~size_t(255);
+    std::vector<char> host(bytes, 0);
+    for (auto &pt : parts)
+        if (std::get<1>(pt)) std::memcpy(host.data() + std::get<2>(pt), std::get<0>(pt), std::get<1>(pt));
+    if (hipMalloc(&b->blob, bytes) != hipSuccess) return TRS_EDEVICE;
+    if (hipMemcpy(b->blob, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(b->blob);
+        return TRS_EDEVICE;
+    }
+    char *bp = static_cast<char *>(b->blob);
+    trs::BatchLaunch &L = b->launch;
+    L.plans = reinterpret_cast<const trs::SpaceView *>(bp + o_views);
+    L.frames = reinterpret_cast<const trs::BatchFrameDev *>(bp + o_frames);
+    L.ctu_frame = reinterpret_cast<const int *>(bp + o_cf);
+    L.item_frame = reinterpret_cast<const int *>(bp + o_if);
+    L.n_frames = n_frames;
+    L.total_ctus = (int)ctu_frame.size();
+    L.total_items = (int)total_items;
+    L.cs = cs;
+    L.block = block ? block : 256;
+    L.rec_max = rec_max;
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+        n_cu = 256;
+    const int occ1 = wgs_per_cu ? wgs_per_cu : trs::batch_occupancy(L.block, rec_max, false);
+    const int occ2 = wgs_per_cu ? wgs_per_cu : trs::batch_occupancy(L.block, rec_max, true);
+    L.grid1 = (int)std::max<long long>(1, std::min<long long>(total_items, (long long)n_cu * occ1));
+    L.grid2 = (int)std::max<long long>(1, std::min<long long>(total_items, (long long)n_cu * occ2));
+    *out = b.release();
+    return TRS_OK;
+}
+
+trs_status trs_batch_workspace(trs_batch batch, size_t *bytes)
+{
+    if (!batch || !bytes) return TRS_EINVAL;
+    *bytes = batch->ws_bytes;
+    return TRS_OK;
+}
+
+trs_status trs_batch_run(trs_batch batch, void *workspace, size_t ws_bytes, trs_result *out_dev,
+                         hipStream_t stream)
+{
+    if (!batch || !out_dev) return TRS_EINVAL;
+    if (!workspace || ws_bytes < batch->ws_bytes || reinterpret_cast<uintptr_t>(workspace) % 256)
+        return TRS_EWORKSPACE;
+    return trs::launch_batch(batch->launch, static_cast<char *>(workspace), out_dev, stream) == hipSuccess
+               ? TRS_OK
+               : TRS_EDEVICE;
+}
+
+trs_status trs_batch_frame_arrays(trs_batch batch, void *workspace, int32_t frame, trs_feat *feat,
+                                  uint32_t **cost)
+{
+    if (!batch || !workspace || frame < 0 || frame >= (int32_t)batch->frames.size()) return TRS_EINVAL;
+    char *ws = static_cast<char *>(workspace);
+    const trs::BatchFrameDev &fd = batch->frames[frame];
+    if (feat) {
+        feat->s1 = reinterpret_cast<uint32_t *>(ws + fd.o_s1);
+        feat->grad = reinterpret_cast<uint32_t *>(ws + fd.o_grad);
+        feat->tex = reinterpret_cast<uint32_t *>(ws + fd.o_tex);
+        feat->mean = reinterpret_cast<uint32_t *>(ws + fd.o_mean);
+        feat->var = reinterpret_cast<uint32_t *>(ws + fd.o_var);
+        feat->s2 = reinterpret_cast<uint64_t *>(ws + fd.o_s2);
+    }
+    if (cost) *cost = reinterpret_cast<uint32_t *>(ws + fd.o_cost);
+    return TRS_OK;
+}
+
+void trs_batch_destroy(trs_batch batch)
+{
+    if (!batch) return;
+    if (batch->blob) (void)hipFree(batch->blob);
+    delete batch;
 }
 
 void trs_release_plans(void)

@@ -70,17 +70,20 @@ __device__ __forceinline__ int xcd_item(int b, int G)
     return xcd * q + min(xcd, rm) + local;
 }
 
+// Statistics of CTU `ctu` (raster index) of one frame, by the whole work-group of
+// (CS / 8) * 16 threads.
 template <int CS>
-__global__ void __launch_bounds__((CS / 8) * 16)
-k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, int W,
-           uint32_t *__restrict__ o_s1, unsigned long long *__restrict__ o_s2,
-           uint32_t *__restrict__ o_g, uint32_t *__restrict__ o_tex,
-           uint32_t *__restrict__ o_mean, uint32_t *__restrict__ o_var)
+__device__ __forceinline__ void features_ctu(const uint16_t *__restrict__ luma, long long stride,
+                                             int w, int h, int W, int ctu,
+                                             uint32_t *__restrict__ o_s1,
+                                             unsigned long long *__restrict__ o_s2,
+                                             uint32_t *__restrict__ o_g, uint32_t *__restrict__ o_tex,
+                                             uint32_t *__restrict__ o_mean,
+                                             uint32_t *__restrict__ o_var)
 {
     constexpr int CH = CS / 8;           // 8-sample chunks per CTU row
     constexpr int NT = CH * 16;          // threads: CH chunks x 16 row groups
     constexpr int R = CS / 16;           // rows per row group
-    const int ctu = xcd_item(blockIdx.x, gridDim.x);
     const int cy = ctu / W, cx = ctu - cy * W, tid = threadIdx.x;
     const int chunk = tid % CH, grp = tid / CH;
     const int x0 = cx * CS + chunk * 8;
@@ -191,6 +194,17 @@ k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, in
         o_mean[ctu] = (uint32_t)(t1 / n);
         o_var[ctu] = (uint32_t)((n * t2 - (unsigned long long)t1 * t1) / (n * n));
     }
+}
+
+template <int CS>
+__global__ void __launch_bounds__((CS / 8) * 16)
+k_features(const uint16_t *__restrict__ luma, long long stride, int w, int h, int W,
+           uint32_t *__restrict__ o_s1, unsigned long long *__restrict__ o_s2,
+           uint32_t *__restrict__ o_g, uint32_t *__restrict__ o_tex,
+           uint32_t *__restrict__ o_mean, uint32_t *__restrict__ o_var)
+{
+    features_ctu<CS>(luma, stride, w, h, W, xcd_item(blockIdx.x, gridDim.x), o_s1, o_s2, o_g,
+                     o_tex, o_mean, o_var);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -326,20 +340,20 @@ k_sat_lds(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__res
     }
 }
 
-// Cost map fused with the LDS prefix sums (same grids as k_sat_lds).
-__global__ void __launch_bounds__(256)
-k_cost_sat(int W, int H, const uint32_t *__restrict__ tex, const uint32_t *__restrict__ prev,
-           uint32_t a, uint32_t b, uint32_t wp, uint32_t *__restrict__ cost, uint32_t *flags,
-           const uint32_t *__restrict__ s1, const unsigned long long *__restrict__ s2,
-           long long *satT, long long *satS1, long long *satS2, WsHeader *hdr)
+// Cost map fused with the LDS prefix sums (same grids as k_sat_lds), by one work-group.
+__device__ void cost_sat_body(int W, int H, const uint32_t *__restrict__ tex,
+                              const uint32_t *__restrict__ prev, uint32_t a, uint32_t b,
+                              uint32_t wp, uint32_t *__restrict__ cost, uint32_t *flags,
+                              const uint32_t *__restrict__ s1,
+                              const unsigned long long *__restrict__ s2, long long *satT,
+                              long long *satS1, long long *satS2)
 {
     __shared__ long long lT[kSatLds], l1[kSatLds], l2[kSatLds];
     __shared__ uint32_t lc[kSatLds];
-    const int tid = threadIdx.x;
-    (void)hdr;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const int S = W + 1, n = W * H;
     bool any_over = false;
-    for (int i = tid; i < n; i += blockDim.x) {
+    for (int i = tid; i < n; i += nt) {
         bool over;
         const uint32_t v = cost_of(tex[i], prev, i, a, b, wp, &over);
         cost[i] = v;
@@ -348,7 +362,7 @@ k_cost_sat(int W, int H, const uint32_t *__restrict__ tex, const uint32_t *__res
     }
     if (any_over && flags) atomicOr(flags, 1u);
     __syncthreads();
-    for (int y = tid; y < H; y += blockDim.x) {
+    for (int y = tid; y < H; y += nt) {
         long long aT = 0, a1 = 0, a2 = 0;
         const int e0 = (y + 1) * S;
         lT[e0] = l1[e0] = l2[e0] = 0;
@@ -362,7 +376,7 @@ k_cost_sat(int W, int H, const uint32_t *__restrict__ tex, const uint32_t *__res
         }
     }
     __syncthreads();
-    for (int x = tid; x <= W; x += blockDim.x) {
+    for (int x = tid; x <= W; x += nt) {
         long long aT = 0, a1 = 0, a2 = 0;
         satT[x] = satS1[x] = satS2[x] = 0;
         for (int y = 1; y <= H; y++) {
@@ -374,6 +388,16 @@ k_cost_sat(int W, int H, const uint32_t *__restrict__ tex, const uint32_t *__res
             satS2[y * S + x] = a2;
         }
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_cost_sat(int W, int H, const uint32_t *__restrict__ tex, const uint32_t *__restrict__ prev,
+           uint32_t a, uint32_t b, uint32_t wp, uint32_t *__restrict__ cost, uint32_t *flags,
+           const uint32_t *__restrict__ s1, const unsigned long long *__restrict__ s2,
+           long long *satT, long long *satS1, long long *satS2, WsHeader *hdr)
+{
+    (void)hdr;
+    cost_sat_body(W, H, tex, prev, a, b, wp, cost, flags, s1, s2, satT, satS1, satS2);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -584,62 +608,23 @@ __device__ void final_block(const SpaceView &sp, const Partial *__restrict__ par
     }
 }
 
-// One work item per work-group.  Phase 1 builds the item's tile-option records in LDS: for
-// a column span, tile row and (k, split offsets) option, the largest slice time (Eq. 1)
-// and, in step 2, the summed per-slice ceil-SSE (Eq. 2).  Phase 2 scores the item's
-// candidates, one per lane: T~(P) is the max of its tiles' record times, Q(P) the sum of
-// their record sums.  STAGE: the prefix sums the records read are first copied to LDS.
-//
-// Step 1 writes each item's smallest T~(P); k_live turns those into T~min, the Eq. 4
-// bound and the list of items that can hold a step-2 candidate; step 2 runs over that
-// list only; k_final reduces its partials and decodes the winner.
-template <int BS, bool P2, bool STAGE>
-__global__ void __launch_bounds__(BS)
-k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
-         const long long *__restrict__ satS1, const long long *__restrict__ satS2,
-         WsHeader *hdr, unsigned long long *__restrict__ item_min, int *__restrict__ live,
-         Partial *__restrict__ part, int lam_num, int lam_den, trs_result *out, int dt, int dr)
+// Scores one work item with the whole work-group: phase 1 builds its tile-option records
+// (recT, and recQ in step 2), phase 2 scores its candidates one per lane.  The result is
+// valid in thread 0: the item's smallest T~(P) (step 1) or its best (Q, T~, rank) within
+// `bound` (step 2).
+template <int BS, bool P2>
+__device__ __forceinline__ void search_item(const SpaceView &sp, const ItemDev &it,
+                                            const long long *sT, const long long *s1t,
+                                            const long long *s2t, unsigned long long bound,
+                                            unsigned long long *recT, unsigned long long *recQ,
+                                            unsigned long long &tbest_out, Key2 &best_out)
 {
-    extern __shared__ __align__(16) unsigned char lds[];
-    unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds + L.recT);
-    unsigned long long *recQ = reinterpret_cast<unsigned long long *>(lds + (P2 ? L.recQ : L.recT));
     constexpr int NW = BS / kWave;
     __shared__ unsigned long long redq[NW], redt[NW];
     __shared__ long long redr[NW];
     __shared__ int redf[NW];
-
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int S = sp.W + 1;
-    int slot, item;
-    if (P2) {
-        const int n_live = hdr->n_live;
-        if ((int)blockIdx.x >= n_live) return;      // the item list is shorter than the grid
-        slot = xcd_item(blockIdx.x, n_live);
-        item = live[slot];
-    } else {
-        slot = item = xcd_item(blockIdx.x, gridDim.x);
-    }
-    const long long *sT = satT, *s1t = satS1, *s2t = satS2;
-    if (STAGE) {                       // independent of the item: overlaps its load latency
-        long long *lT = reinterpret_cast<long long *>(lds + L.satT);
-        long long *l1 = reinterpret_cast<long long *>(lds + (P2 ? L.satS1 : L.satT));
-        long long *l2 = reinterpret_cast<long long *>(lds + (P2 ? L.satS2 : L.satT));
-        const int n = S * (sp.H + 1);
-        for (int e = tid; e < n; e += BS) {
-            lT[e] = satT[e];
-            if (P2) {
-                l1[e] = satS1[e];
-                l2[e] = satS2[e];
-            }
-        }
-        sT = lT;
-        s1t = l1;
-        s2t = l2;
-    }
-    const ItemDev it = sp.items[item];
-    const unsigned long long bound = P2 ? hdr->bound : kNone;
-    if (STAGE) __syncthreads();
-
     for (int rid = tid; rid < it.n_rec; rid += BS) {
         const uint32_t d0 = sp.rdesc[2 * (it.rec_off + rid)];
         const int opt = (int)sp.rdesc[2 * (it.rec_off + rid) + 1];
@@ -693,7 +678,7 @@ k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
         if (tid == 0) {
             unsigned long long bt = kNone;
             for (int i = 0; i < NW; i++) bt = min(bt, redt[i]);
-            item_min[item] = bt;
+            tbest_out = bt;
         }
     } else {
 #pragma unroll
@@ -713,8 +698,68 @@ k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
                 const Key2 o{redq[i], redt[i], redr[i], redf[i]};
                 if (key_less(o, b)) b = o;
             }
-            part[slot] = Partial{b.q, b.t, b.rank, item, b.f, n, 0};
+            best_out = b;
         }
+    }
+}
+
+// One work item per work-group.  Phase 1 builds the item's tile-option records in LDS: for
+// a column span, tile row and (k, split offsets) option, the largest slice time (Eq. 1)
+// and, in step 2, the summed per-slice ceil-SSE (Eq. 2).  Phase 2 scores the item's
+// candidates, one per lane: T~(P) is the max of its tiles' record times, Q(P) the sum of
+// their record sums.  STAGE: the prefix sums the records read are first copied to LDS.
+//
+// Step 1 writes each item's smallest T~(P); k_live turns those into T~min, the Eq. 4
+// bound and the list of items that can hold a step-2 candidate; step 2 runs over that
+// list only; k_final reduces its partials and decodes the winner.
+template <int BS, bool P2, bool STAGE>
+__global__ void __launch_bounds__(BS)
+k_search(SpaceView sp, LdsMap L, const long long *__restrict__ satT,
+         const long long *__restrict__ satS1, const long long *__restrict__ satS2,
+         WsHeader *hdr, unsigned long long *__restrict__ item_min, int *__restrict__ live,
+         Partial *__restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds + L.recT);
+    unsigned long long *recQ = reinterpret_cast<unsigned long long *>(lds + (P2 ? L.recQ : L.recT));
+    const int tid = threadIdx.x;
+    const int S = sp.W + 1;
+    int slot, item;
+    if (P2) {
+        const int n_live = hdr->n_live;
+        if ((int)blockIdx.x >= n_live) return;      // the item list is shorter than the grid
+        slot = xcd_item(blockIdx.x, n_live);
+        item = live[slot];
+    } else {
+        slot = item = xcd_item(blockIdx.x, gridDim.x);
+    }
+    const long long *sT = satT, *s1t = satS1, *s2t = satS2;
+    if (STAGE) {                       // independent of the item: overlaps its load latency
+        long long *lT = reinterpret_cast<long long *>(lds + L.satT);
+        long long *l1 = reinterpret_cast<long long *>(lds + (P2 ? L.satS1 : L.satT));
+        long long *l2 = reinterpret_cast<long long *>(lds + (P2 ? L.satS2 : L.satT));
+        const int n = S * (sp.H + 1);
+        for (int e = tid; e < n; e += BS) {
+            lT[e] = satT[e];
+            if (P2) {
+                l1[e] = satS1[e];
+                l2[e] = satS2[e];
+            }
+        }
+        sT = lT;
+        s1t = l1;
+        s2t = l2;
+    }
+    const ItemDev it = sp.items[item];
+    const unsigned long long bound = P2 ? hdr->bound : kNone;
+    if (STAGE) __syncthreads();
+
+    unsigned long long tb;
+    Key2 bk;
+    search_item<BS, P2>(sp, it, sT, s1t, s2t, bound, recT, recQ, tb, bk);
+    if (tid == 0) {
+        if (!P2) item_min[item] = tb;
+        else part[slot] = Partial{bk.q, bk.t, bk.rank, item, bk.f, it.n_ent, 0};
     }
 }
 
@@ -821,13 +866,11 @@ void launch_pass(const SearchArgs &a, const WsPtrs &w, hipStream_t s)
     if (satb <= kStageLimit) {
         const LdsMap L = lds_map(a.sp, P2, true);
         hipLaunchKernelGGL((k_search<BS, P2, true>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, w.satT,
-                           w.satS1, w.satS2, w.hdr, w.imin, w.live, w.part, a.lam_num, a.lam_den,
-                           a.out, a.dt, a.dr);
+                           w.satS1, w.satS2, w.hdr, w.imin, w.live, w.part);
     } else {
         const LdsMap L = lds_map(a.sp, P2, false);
         hipLaunchKernelGGL((k_search<BS, P2, false>), dim3(G), dim3(BS), L.bytes, s, a.sp, L, w.satT,
-                           w.satS1, w.satS2, w.hdr, w.imin, w.live, w.part, a.lam_num, a.lam_den,
-                           a.out, a.dt, a.dr);
+                           w.satS1, w.satS2, w.hdr, w.imin, w.live, w.part);
     }
 }
 
@@ -860,6 +903,160 @@ hipError_t launch_after_sat(const SearchArgs &a, hipStream_t s)
     }
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------------------
+
+template <int CS>
+__global__ void __launch_bounds__((CS / 8) * 16)
+k_features_batch(const BatchFrameDev *__restrict__ frames, const int *__restrict__ ctu_frame,
+                 char *ws)
+{
+    const int g = xcd_item(blockIdx.x, gridDim.x);
+    const BatchFrameDev fr = frames[ctu_frame[g]];
+    features_ctu<CS>(fr.luma, fr.stride, fr.w, fr.h, fr.W, g - fr.ctu_base,
+                     reinterpret_cast<uint32_t *>(ws + fr.o_s1),
+                     reinterpret_cast<unsigned long long *>(ws + fr.o_s2),
+                     reinterpret_cast<uint32_t *>(ws + fr.o_grad),
+                     reinterpret_cast<uint32_t *>(ws + fr.o_tex),
+                     reinterpret_cast<uint32_t *>(ws + fr.o_mean),
+                     reinterpret_cast<uint32_t *>(ws + fr.o_var));
+}
+
+// One work-group per frame: cost map (overflow flag in the frame's header) and SATs.
+__global__ void __launch_bounds__(256)
+k_cost_sat_batch(const BatchFrameDev *__restrict__ frames, char *ws)
+{
+    const BatchFrameDev fr = frames[blockIdx.x];
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(ws + fr.o_hdr);
+    if (threadIdx.x == 0) hdr->pad0 = 0;
+    __syncthreads();
+    cost_sat_body(fr.W, fr.H, reinterpret_cast<const uint32_t *>(ws + fr.o_tex), fr.prev, fr.a,
+                  fr.b, fr.wp, reinterpret_cast<uint32_t *>(ws + fr.o_cost),
+                  reinterpret_cast<uint32_t *>(&hdr->pad0),
+                  reinterpret_cast<const uint32_t *>(ws + fr.o_s1),
+                  reinterpret_cast<const unsigned long long *>(ws + fr.o_s2),
+                  reinterpret_cast<long long *>(ws + fr.o_satT),
+                  reinterpret_cast<long long *>(ws + fr.o_satS1),
+                  reinterpret_cast<long long *>(ws + fr.o_satS2));
+}
+
+// Persistent search over every (frame, item) of the batch: work-group b takes a contiguous
+// range of the flat item list (ranges of neighbouring b stay on one XCD).  Step 2 skips
+// items whose step-1 minimum exceeds their frame's Eq. 4 bound.
+template <int BS, bool P2>
+__global__ void __launch_bounds__(BS)
+k_search_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restrict__ frames,
+               const int *__restrict__ item_frame, int total, char *ws,
+               unsigned long long *__restrict__ item_min, Partial *__restrict__ part, int rec_max)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds);
+    unsigned long long *recQ = recT + rec_max;
+    const int tid = threadIdx.x;
+    const int G = gridDim.x, b = xcd_item(blockIdx.x, G);
+    const int beg = (int)((long long)total * b / G), end = (int)((long long)total * (b + 1) / G);
+    int cur = -1;
+    BatchFrameDev fr{};
+    for (int g = beg; g < end; g++) {
+        const int f = item_frame[g];
+        if (f != cur) {
+            fr = frames[f];
+            cur = f;
+        }
+        const SpaceView &sp = plans[fr.plan];
+        const int i = g - fr.item_base;
+        unsigned long long bound = kNone;
+        if (P2) {
+            bound = reinterpret_cast<const WsHeader *>(ws + fr.o_hdr)->bound;
+            if (item_min[g] > bound) {
+                if (tid == 0) part[g] = Partial{kNone, kNone, LLONG_MAX, i, -1, 0, 0};
+                continue;
+            }
+        }
+        const ItemDev it = sp.items[i];
+        __syncthreads();                             // the previous item's records are read
+        unsigned long long tb;
+        Key2 bk;
+        search_item<BS, P2>(sp, it, reinterpret_cast<const long long *>(ws + fr.o_satT),
+                            reinterpret_cast<const long long *>(ws + fr.o_satS1),
+                            reinterpret_cast<const long long *>(ws + fr.o_satS2), bound, recT,
+                            recQ, tb, bk);
+        if (tid == 0) {
+            if (!P2) item_min[g] = tb;
+            else part[g] = Partial{bk.q, bk.t, bk.rank, i, bk.f, it.n_ent, 0};
+        }
+    }
+}
+
+// One work-group per frame: T~min and the Eq. 4 bound from the frame's item minima.
+__global__ void __launch_bounds__(256)
+k_tmin_batch(const BatchFrameDev *__restrict__ frames,
+             const unsigned long long *__restrict__ item_min, char *ws)
+{
+    constexpr int NW = 256 / kWave;
+    __shared__ unsigned long long rt[NW];
+    const BatchFrameDev fr = frames[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    unsigned long long t = kNone;
+    for (int i = tid; i < fr.n_items; i += 256) t = min(t, item_min[fr.item_base + i]);
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) t = min(t, shfl_xor64(t, m));
+    if (lane == 0) rt[wv] = t;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long tmin = kNone;
+        for (int i = 0; i < NW; i++) tmin = min(tmin, rt[i]);
+        unsigned long long bnd = kNone;
+        if (fr.lam_num >= 0 && tmin != kNone)
+            bnd = tmin * (unsigned long long)(fr.lam_den + fr.lam_num) / (unsigned long long)fr.lam_den;
+        WsHeader *hdr = reinterpret_cast<WsHeader *>(ws + fr.o_hdr);
+        hdr->tmin = tmin;
+        hdr->bound = bnd;
+        hdr->n_live = fr.n_items;
+    }
+}
+
+// One work-group per frame: the frame's winner over its items' partials, decoded.
+__global__ void __launch_bounds__(256)
+k_final_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restrict__ frames,
+              const Partial *__restrict__ part, char *ws, trs_result *out)
+{
+    const BatchFrameDev fr = frames[blockIdx.x];
+    const SpaceView sp = plans[fr.plan];
+    final_block<256>(sp, part + fr.item_base, fr.n_items,
+                     reinterpret_cast<const WsHeader *>(ws + fr.o_hdr),
+                     reinterpret_cast<const long long *>(ws + fr.o_satT),
+                     reinterpret_cast<const long long *>(ws + fr.o_satS1),
+                     reinterpret_cast<const long long *>(ws + fr.o_satS2), out + blockIdx.x,
+                     fr.dt, fr.dr);
+}
+
+template <int BS>
+void launch_batch_search(const BatchLaunch &b, char *ws, hipStream_t s)
+{
+    auto *imin = reinterpret_cast<unsigned long long *>(ws + b.o_item_min);
+    auto *part = reinterpret_cast<Partial *>(ws + b.o_part);
+    hipLaunchKernelGGL((k_search_batch<BS, false>), dim3(b.grid1), dim3(BS),
+                       batch_lds_bytes(b.rec_max, false), s, b.plans, b.frames, b.item_frame,
+                       b.total_items, ws, imin, part, b.rec_max);
+    hipLaunchKernelGGL(k_tmin_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, imin, ws);
+    hipLaunchKernelGGL((k_search_batch<BS, true>), dim3(b.grid2), dim3(BS),
+                       batch_lds_bytes(b.rec_max, true), s, b.plans, b.frames, b.item_frame,
+                       b.total_items, ws, imin, part, b.rec_max);
+}
+
+template <int BS>
+int occupancy_of(int rec_max, bool step2)
+{
+    int n = 0;
+    const int lds = batch_lds_bytes(rec_max, step2);
+    hipError_t e = step2
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search_batch<BS, true>, BS, lds)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search_batch<BS, false>, BS, lds);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
 }  // namespace
 
 WsLayout ws_layout(const Plan &pl)
@@ -935,6 +1132,74 @@ hipError_t launch_partition_tail(const SearchArgs &a, const uint32_t *tex, const
     const hipError_t e = launch_cost_map(a.sp.W * a.sp.H, tex, prev, b, cost, flags, s);
     if (e != hipSuccess) return e;
     return launch_search(a, s);
+}
+
+long long batch_frame_region(int W, int H, BatchFrameDev *fr, long long base)
+{
+    auto up = [](long long v) { return (v + 255) & ~255ll; };
+    const long long n = (long long)W * H, sat = 8ll * (W + 1) * (H + 1);
+    long long o = base;
+    fr->o_s1 = o;   o += up(4 * n);
+    fr->o_grad = o; o += up(4 * n);
+    fr->o_tex = o;  o += up(4 * n);
+    fr->o_mean = o; o += up(4 * n);
+    fr->o_var = o;  o += up(4 * n);
+    fr->o_s2 = o;   o += up(8 * n);
+    fr->o_cost = o; o += up(4 * n);
+    fr->o_hdr = o;  o += up(sizeof(WsHeader));
+    fr->o_satT = o; o += up(sat);
+    fr->o_satS1 = o; o += up(sat);
+    fr->o_satS2 = o; o += up(sat);
+    return o;
+}
+
+int batch_lds_bytes(int rec_max, bool step2)
+{
+    const int rec = rec_max > 0 ? rec_max : 1;
+    return 8 * rec * (step2 ? 2 : 1);
+}
+
+int batch_occupancy(int block, int rec_max, bool step2)
+{
+    switch (block) {
+    case 64: return occupancy_of<64>(rec_max, step2);
+    case 128: return occupancy_of<128>(rec_max, step2);
+    case 512: return occupancy_of<512>(rec_max, step2);
+    default: return occupancy_of<256>(rec_max, step2);
+    }
+}
+
+hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s)
+{
+    switch (b.cs) {
+    case 128:
+        hipLaunchKernelGGL(k_features_batch<128>, dim3(b.total_ctus), dim3(256), 0, s, b.frames,
+                           b.ctu_frame, ws);
+        break;
+    case 64:
+        hipLaunchKernelGGL(k_features_batch<64>, dim3(b.total_ctus), dim3(128), 0, s, b.frames,
+                           b.ctu_frame, ws);
+        break;
+    default:
+        hipLaunchKernelGGL(k_features_batch<32>, dim3(b.total_ctus), dim3(64), 0, s, b.frames,
+                           b.ctu_frame, ws);
+        break;
+    }
+    hipLaunchKernelGGL(k_cost_sat_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, ws);
+    if (b.total_items > 0) {
+        switch (b.block) {
+        case 64: launch_batch_search<64>(b, ws, s); break;
+        case 128: launch_batch_search<128>(b, ws, s); break;
+        case 512: launch_batch_search<512>(b, ws, s); break;
+        default: launch_batch_search<256>(b, ws, s); break;
+        }
+    } else {
+        hipLaunchKernelGGL(k_tmin_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames,
+                           reinterpret_cast<unsigned long long *>(ws + b.o_item_min), ws);
+    }
+    hipLaunchKernelGGL(k_final_batch, dim3(b.n_frames), dim3(256), 0, s, b.plans, b.frames,
+                       reinterpret_cast<const Partial *>(ws + b.o_part), ws, out);
+    return hipGetLastError();
 }
 
 }  // namespace trs

@@ -43,6 +43,37 @@ struct SearchArgs {
     hipEvent_t ev[4];                 // optional timing events (all null when not profiling)
 };
 
+// ---- batched form: many frames of mixed sizes and parameters, one launch per stage ----
+
+// Per-frame descriptor on the device.  o_* are byte offsets of the frame's arrays in the
+// batch workspace.
+struct BatchFrameDev {
+    const uint16_t *luma;
+    long long stride;
+    const uint32_t *prev;
+    uint32_t a, b, wp, pad0;
+    int w, h, W, H;
+    int plan, lam_num, lam_den, dt;
+    int dr, ctu_base, item_base, n_items;
+    long long o_s1, o_grad, o_tex, o_mean, o_var, o_s2, o_cost, o_hdr, o_satT, o_satS1, o_satS2;
+};
+
+struct BatchLaunch {
+    const SpaceView *plans;           // device
+    const BatchFrameDev *frames;      // device
+    const int *ctu_frame, *item_frame;
+    int n_frames, total_ctus, total_items, cs;
+    int block, grid1, grid2, rec_max;
+    long long o_item_min, o_part;     // byte offsets in the workspace
+};
+
+// Byte layout of one frame's region and its size (W x H CTUs).
+long long batch_frame_region(int W, int H, BatchFrameDev *fr, long long base);
+int batch_lds_bytes(int rec_max, bool step2);
+// Work-groups per CU the batched search kernels can keep resident.
+int batch_occupancy(int block, int rec_max, bool step2);
+hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s);
+
 hipError_t launch_features(int w, int h, int cs, const uint16_t *luma, int64_t stride,
                            const trs_feat &out, hipStream_t s);
 hipError_t launch_cost_map(int n, const uint32_t *tex, const uint32_t *prev, trs_blend b,

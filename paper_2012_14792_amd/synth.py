@@ -136,3 +136,40 @@ CONFIGS = {
     "8k_n16": dict(width=7680, height=4320, frames=32, n_threads=16, max_tile_cols=8,
                    max_tile_rows=6, max_rs_per_tile=4, lam=(1, 10), seed=3, drift=8.0),
 }
+
+
+# Search bounds per thread budget (tile columns, tile rows, slices per tile) and the lambda
+# chosen per (resolution, N): Table 1 picks lambda per resolution and thread count; 16
+# threads take the 12-thread choice.
+BOUNDS = {4: (3, 3, 2), 8: (6, 4, 4), 16: (8, 6, 4)}
+LAMBDA = {("fhd", 4): (0, 1), ("fhd", 8): (3, 10), ("fhd", 16): (1, 10),
+          ("uhd", 4): (0, 1), ("uhd", 8): (1, 10), ("uhd", 16): (1, 10),
+          ("8k", 4): (0, 1), ("8k", 8): (1, 10), ("8k", 16): (1, 10)}
+SIZES = {"fhd": (1920, 1080), "uhd": (3840, 2160), "8k": (7680, 4320)}
+
+
+def batch_workload(n_frames: int = 512, seed: int = 4, mix=(1, 2, 1)):
+    """The mixed batch: sizes in proportion fhd:uhd:8k = mix, in seeded order, and a thread
+    budget drawn from {4, 8, 16} per frame.
+
+    Returns a list of (size, index_within_size, N).  Frame i of a size is frame i of that
+    size's drifting sequence (generator seed `seed` * 10 + size number, drift 8 px/frame).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tot = sum(mix)
+    counts = [n_frames * m // tot for m in mix]
+    counts[1] += n_frames - sum(counts)
+    names = ["fhd"] * counts[0] + ["uhd"] * counts[1] + ["8k"] * counts[2]
+    order = rng.permutation(len(names))
+    ns = rng.choice([4, 8, 16], size=n_frames)
+    seen = {"fhd": 0, "uhd": 0, "8k": 0}
+    out = []
+    for i, k in enumerate(order):
+        name = names[k]
+        out.append((name, seen[name], int(ns[i])))
+        seen[name] += 1
+    return out
+
+
+def batch_sequence_seed(name: str, seed: int = 4) -> int:
+    return seed * 10 + ["fhd", "uhd", "8k"].index(name)

@@ -1,0 +1,133 @@
+"""GPU parity of the batched form: one launch sequence for many frames of mixed sizes and
+thread budgets must give, for every frame, exactly the per-frame launch's result, which
+must equal the oracle's."""
+import numpy as np
+import pytest
+
+from helpers import assert_same_result, oracle_params, to_device
+from paper_2012_14792_amd import binding as B
+from paper_2012_14792_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+
+
+def _mixed_frames(orc, spec, seed=7):
+    """spec: list of (size, N, lam); frames are consecutive frames of per-size sequences."""
+    import torch
+    gens, counts, out = {}, {}, []
+    for name, N, lam in spec:
+        w, h = synth.SIZES[name]
+        if name not in gens:
+            gens[name] = synth.SequenceGenerator(w, h, synth.batch_sequence_seed(name, seed), 8.0)
+            counts[name] = 0
+        f = counts[name]
+        counts[name] += 1
+        luma = gens[name].frame(f)
+        tex = orc.features(gens[name].frame(max(f - 1, 0)))["tex"]
+        prev = synth.ctu_times(tex, synth.ar1_eps(tex.size, 1, 100 + len(out))[0])
+        C, R, K = synth.BOUNDS[N]
+        out.append(dict(name=name, width=w, height=h, luma_np=luma, prev_np=prev,
+                        params=B.make_params(N, C, R, K, lam=lam), luma=to_device(luma),
+                        prev=torch.from_numpy(prev.view(np.int32)).cuda()))
+    return out
+
+
+SPEC = [("fhd", 4, (0, 1)), ("uhd", 8, (1, 10)), ("fhd", 16, (1, 10)), ("fhd", 8, (3, 10)),
+        ("uhd", 4, (0, 1)), ("fhd", 4, (-1, 1)), ("uhd", 16, (1, 10)), ("fhd", 8, (0, 1))]
+
+
+def test_batch_matches_per_frame_and_oracle(orc):
+    import torch
+    frames = _mixed_frames(orc, SPEC)
+    batch = B.Batch(frames)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    got = batch.results()
+    for i, fr in enumerate(frames):
+        part = B.Partitioner(fr["width"], fr["height"], fr["params"])
+        single = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        part.enqueue(fr["luma"], fr["prev"], out=single)
+        torch.cuda.synchronize()
+        assert torch.equal(single, batch.out[i]), f"frame {i} differs from its per-frame launch"
+        if fr["name"] == "fhd" or i == 1:
+            ref = orc.partition(fr["luma_np"], fr["prev_np"], oracle_params(orc, fr["params"]))
+            assert_same_result(got[i], ref, f"batch frame {i}")
+    batch.close()
+
+
+def test_batch_features_and_cost_in_workspace(orc):
+    import torch
+    frames = _mixed_frames(orc, SPEC[:3])
+    batch = B.Batch(frames)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    for i, fr in enumerate(frames):
+        feat, cost = batch.frame_arrays(i)
+        W, H = (fr["width"] + 127) // 128, (fr["height"] + 127) // 128
+        base = batch.ws.data_ptr()
+        def view(ptr, n, dt):
+            off = ptr - base
+            return batch.ws[off:off + n * np.dtype(dt).itemsize].cpu().numpy().view(dt)
+        o = orc.features(fr["luma_np"])
+        for k in ("s1", "grad", "tex", "mean", "var"):
+            assert np.array_equal(view(getattr(feat, k), W * H, np.uint32), o[k]), k
+        assert np.array_equal(view(feat.s2, W * H, np.uint64), o["s2"])
+        c, _ = orc.cost_map(o["tex"], fr["prev_np"])
+        assert np.array_equal(view(cost, W * H, np.uint32), c)
+    batch.close()
+
+
+@pytest.mark.parametrize("block,wgs", [(64, 0), (128, 2), (512, 1), (256, 3)])
+def test_batch_schedules_do_not_change_results(orc, block, wgs):
+    import torch
+    frames = _mixed_frames(orc, SPEC)
+    ref = B.Batch(frames)
+    ref.enqueue()
+    other = B.Batch(frames, block=block, wgs_per_cu=wgs)
+    other.enqueue()
+    torch.cuda.synchronize()
+    assert torch.equal(ref.out, other.out)
+    ref.close()
+    other.close()
+
+
+def test_batch_graph_replays(orc):
+    import torch
+    frames = _mixed_frames(orc, SPEC)
+    batch = B.Batch(frames)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    eager = batch.out.clone()
+    g = batch.capture()
+    for rep in range(3):
+        batch.out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(batch.out, eager), f"replay {rep}"
+        batch.enqueue()                       # eager work between replays
+        torch.cuda.synchronize()
+    batch.close()
+
+
+def test_batch_with_infeasible_frame(orc):
+    import torch
+    frames = _mixed_frames(orc, SPEC[:2])
+    frames[0]["params"] = B.make_params(4, 3, 3, 2, area_k=1)     # nothing feasible
+    batch = B.Batch(frames)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    got = batch.results()
+    assert got[0]["status"] == 1
+    for i, fr in enumerate(frames):
+        ref = orc.partition(fr["luma_np"], fr["prev_np"], oracle_params(orc, fr["params"]))
+        assert_same_result(got[i], ref, f"frame {i}")
+    batch.close()
