@@ -66,6 +66,7 @@ def main():
     import numpy as np
     import torch
 
+    from paper_2012_14792_amd import autotune
     from paper_2012_14792_amd import binding as B
     from paper_2012_14792_amd import synth
 
@@ -75,6 +76,8 @@ def main():
     params = B.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
                            cfg["max_rs_per_tile"], lam=cfg["lam"], sched_block=args.sched_block,
                            sched_item=args.sched_item)
+    if not (args.sched_block or args.sched_item):
+        params = autotune.tuned_params(w, h, params)       # cached schedule, if any
     frame = B.make_frame(w, h)
     stats = B.trs_search_stats(frame, params)
     W, H = B.ctu_dims(frame)
@@ -261,7 +264,7 @@ def main():
                                f"one frame per launch sequence",
                    "frames": F, "width": w, "height": h, "n_threads": 8,
                    "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
-                   "sched_block": args.sched_block or 256, "sched_item": args.sched_item or 512,
+                   "sched_block": params.sched_block or 256, "sched_item": params.sched_item or 512,
                    "streams": S,
                    "timing": f"HIP graph of one step ({F} trs_partition calls over {S} streams), replayed K times"},
         "candidates_scored_per_s": round(fps * stats["candidates"], 1),
@@ -287,11 +290,15 @@ def run_batch(args):
     import numpy as np
     import torch
 
+    from paper_2012_14792_amd import autotune
     from paper_2012_14792_amd import binding as B
     from paper_2012_14792_amd import synth
 
     torch.cuda.set_device(0)
     spec = synth.batch_workload(args.batch_frames)
+    tuned = (autotune.load(f"{autotune.arch()}|batch512") or {}) if not args.sched_block else {}
+    block = args.sched_block or tuned.get("block", 0)
+    wgs = args.wgs_per_cu or tuned.get("wgs_per_cu", 0)
     t0 = time.perf_counter()
     gens = {n: synth.SequenceGenerator(*synth.SIZES[n], synth.batch_sequence_seed(n), 8.0)
             for n in ("fhd", "uhd", "8k")}
@@ -303,11 +310,14 @@ def run_batch(args):
     params = []
     for n, _, N in spec:
         C, R, K = synth.BOUNDS[N]
-        params.append(B.make_params(N, C, R, K, lam=synth.LAMBDA[(n, N)], sched_block=args.sched_block,
-                                    sched_item=args.sched_item))
+        p = B.make_params(N, C, R, K, lam=synth.LAMBDA[(n, N)], sched_block=args.sched_block,
+                          sched_item=args.sched_item)
+        if not (args.sched_block or args.sched_item):
+            p = autotune.tuned_params(*synth.SIZES[n], p)
+        params.append(p)
     items = [dict(width=synth.SIZES[n][0], height=synth.SIZES[n][1], params=params[i], luma=lumas[i],
                   prev=prevs[i]) for i, (n, _, _) in enumerate(spec)]
-    batch = B.Batch(items, block=args.sched_block, wgs_per_cu=args.wgs_per_cu)
+    batch = B.Batch(items, block=block, wgs_per_cu=wgs)
     # measured times of each frame from its texture (GPU features of the batch itself)
     batch.enqueue()
     torch.cuda.synchronize()
@@ -429,7 +439,7 @@ def run_batch(args):
         "config": {"workload": f"batch of {len(spec)} frames: 1080p/4K/8K 1:2:1, N from {{4,8,16}}, "
                                f"one batched launch sequence (persistent search) per step, graph-replayed",
                    "frames": len(spec), "candidates": cands, "feasible": feas,
-                   "block": args.sched_block or 256, "wgs_per_cu": args.wgs_per_cu},
+                   "block": block or 256, "wgs_per_cu": wgs},
         "per_frame_value": round(fps_p, 3),
         "batched_over_per_frame": round(fps_b / fps_p, 3),
         "candidates_scored_per_s": round(cands * args.steps / el_b, 1),

@@ -113,7 +113,8 @@ typedef struct trs_search_params {
  *                 T~(P), then by smaller rank;
  *   n_enumerated  |C|; n_feasible: candidates passing the area rule;
  *   n_step2       candidates scored in step 2: a work item whose step-1 minimum already
- *                 exceeds the Eq. 4 bound cannot hold a step-2 candidate and is skipped;
+ *                 exceeds the Eq. 4 bound cannot hold a step-2 candidate and is skipped
+ *                 (a work count: it depends on the schedule, unlike every other field);
  *   uniform_rank, t_unif, q_unif: rank and scores of the uniform c_u x r_u grid
  *                 (c_u r_u = N, most square, c_u >= r_u, one RS per tile);
  *   status        TRS_OK or TRS_ENOFEASIBLE;
