@@ -47,8 +47,10 @@ def main():
     ap.add_argument("--sched-block", type=int, default=0)
     ap.add_argument("--sched-item", type=int, default=0)
     ap.add_argument("--streams", type=int, default=8, help="frames in flight (one stream each)")
-    ap.add_argument("--workload", default="uhd_seq", choices=["uhd_seq", "batch512"],
-                    help="uhd_seq: the 64-frame 4K sequence; batch512: 512 mixed frames in one batch")
+    ap.add_argument("--workload", default="uhd_seq", choices=["uhd_seq", "batch512", "mlp"],
+                    help="uhd_seq: the 64-frame 4K sequence; batch512: 512 mixed frames in one batch; "
+                         "mlp: training steps of the learned CTU-time predictor")
+    ap.add_argument("--mlp-batch", type=int, default=65536)
     ap.add_argument("--batch-frames", type=int, default=512)
     ap.add_argument("--wgs-per-cu", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -56,6 +58,8 @@ def main():
     args = ap.parse_args()
     if args.workload == "batch512":
         return run_batch(args)
+    if args.workload == "mlp":
+        return run_mlp(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build partitions frames on a single MI355X "
@@ -445,6 +449,156 @@ def run_batch(args):
         "candidates_scored_per_s": round(cands * args.steps / el_b, 1),
         "cpu_baseline": cpu,
         "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# fp32 FMA-counted flops per sample of the perceptron's matrix products (10 -> 64 -> 64 -> 1)
+MLP_FWD_FLOPS = 2 * (64 * 10 + 64 * 64 + 64)
+# backward: dz1 = W2^T dz2, dW2, dW1, dW3 (the products; GELU derivatives not counted)
+MLP_BWD_FLOPS = 2 * (64 * 64 + 64 * 64 + 64 * 10 + 64)
+PEAK_FP32_TFLOPS = 157.3
+
+
+def run_mlp(args):
+    """Training steps of the learned per-CTU time predictor: forward kernel, backward
+    kernels, torch's Adam, on batches of `--mlp-batch` samples drawn from a resident pool of
+    inputs shaped like the training pairs.  Also times one 4K frame's inference (inputs,
+    forward, time map)."""
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2012_14792_amd import binding as B
+    from paper_2012_14792_amd.mlp import TimeMLP
+
+    torch.cuda.set_device(0)
+    nb = args.mlp_batch
+    pool = 1 << 21
+    g = torch.Generator(device="cuda").manual_seed(7)
+    # inputs in the ranges of the training pairs: textures, variances, means, times (us)
+    scale = torch.tensor([500, 4000, 1000, 500, 500, 500, 500, 3000, 3000, 1], device="cuda")
+    X = torch.rand((pool, 10), generator=g, device="cuda") * scale
+    T = torch.rand(pool, generator=g, device="cuda") * 3
+    m = TimeMLP(seed=0)
+    m.fit_norm(X)
+    opt = torch.optim.Adam(m.parameters(), lr=1e-3)
+    idx = [torch.randint(0, pool, (nb,), generator=g, device="cuda") for _ in range(16)]
+    xs = [X[i].contiguous() for i in idx]
+    ts = [T[i].contiguous() for i in idx]
+
+    def step(k):
+        y = m(xs[k % 16])
+        loss = torch.mean((y - ts[k % 16]) ** 2)
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+
+    for k in range(max(args.warmup, 1)):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sps = nb * args.steps / el
+    log(f"mlp training: {sps / 1e6:.2f} M samples/s ({el / args.steps * 1e3:.3f} ms/step of {nb})")
+
+    # kernel durations with events on the launching stream, at the training batch size
+    ws = [p.detach() for p in m.parameters()]
+    y = torch.empty(nb, device="cuda")
+    z1 = torch.empty((64, nb), device="cuda")
+    z2 = torch.empty((64, nb), device="cuda")
+    dy = torch.randn(nb, device="cuda")
+    grads = [torch.empty_like(p) for p in ws]
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = max(args.steps, 10)
+    B.trs_mlp_forward(ws, m.norm, xs[0], y, z1, z2)
+    B.trs_mlp_backward(ws, m.norm, xs[0], z1, z2, dy, grads)
+    torch.cuda.synchronize()
+    fwd_ms = bwd_ms = 0.0
+    for _ in range(reps):
+        e[0].record()
+        B.trs_mlp_forward(ws, m.norm, xs[0], y, z1, z2)
+        e[1].record()
+        B.trs_mlp_backward(ws, m.norm, xs[0], z1, z2, dy, grads)
+        e[2].record()
+        torch.cuda.synchronize()
+        fwd_ms += e[0].elapsed_time(e[1])
+        bwd_ms += e[1].elapsed_time(e[2])
+    fwd_ms /= reps
+    bwd_ms /= reps
+    fwd_tf = MLP_FWD_FLOPS * nb / (fwd_ms * 1e-3) / 1e12
+    bwd_tf = MLP_BWD_FLOPS * nb / (bwd_ms * 1e-3) / 1e12
+
+    # one 4K frame's inference: inputs -> forward -> time map (2040 CTUs)
+    frame = B.make_frame(3840, 2160)
+    W, H = B.ctu_dims(frame)
+    feats = B.alloc_features(frame)
+    lum = torch.randint(0, 1024, (2160, 3840), dtype=torch.int16, generator=g, device="cuda")
+    B.trs_features(frame, lum, feats)
+    prev = torch.randint(200, 3000, (W * H,), dtype=torch.int32, generator=g, device="cuda")
+    x4 = torch.empty((W * H, 10), device="cuda")
+    cost = torch.empty(W * H, dtype=torch.int32, device="cuda")
+
+    def infer():
+        B.trs_mlp_inputs(frame, feats, prev, x4)
+        m.cost_map(frame, x4, feats["tex"], prev, cost=cost)
+
+    infer()
+    torch.cuda.synchronize()
+    e[0].record()
+    for _ in range(reps):
+        infer()
+    e[1].record()
+    torch.cuda.synchronize()
+    inf_us = e[0].elapsed_time(e[1]) / reps * 1e3
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import mlp_ref
+        n_cpu = 1 << 16
+        p = {k: v.cpu().double().numpy() for k, v in zip(("w1", "b1", "w2", "b2", "w3", "b3"), ws)}
+        xc = X[:n_cpu].cpu().double().numpy()
+        mean = np.array(list(m.norm.mean))
+        inv = np.array(list(m.norm.inv_std))
+        dyc = dy[:n_cpu].cpu().double().numpy() if nb >= n_cpu else np.ones(n_cpu)
+        t1 = time.perf_counter()
+        reps_cpu = 0
+        while True:
+            _, cache = mlp_ref.forward(p, xc, mean, inv)
+            mlp_ref.backward(p, cache, dyc)
+            reps_cpu += 1
+            if time.perf_counter() - t1 > 10.0:
+                break
+        wall = time.perf_counter() - t1
+        cores = min(len(os.sched_getaffinity(0)), args.cpu_threads)
+        cpu = {"value": round(n_cpu * reps_cpu / wall, 1), "unit": "samples/s (forward + backward)",
+               "cores": cores, "kind": "oracle",
+               "sample": f"FP64 reference forward + backward on {n_cpu} samples, {reps_cpu} passes, "
+                         f"{wall:.1f} s wall (numpy matrix products may use up to {cores} threads)"}
+        log(f"cpu baseline: {cpu['value']:.0f} samples/s")
+
+    out = {
+        "metric": "learned CTU-time predictor training samples/s (forward + backward + Adam, 1 GPU)",
+        "value": round(sps, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"10-64-64-1 GELU perceptron, batches of {nb} samples from a resident "
+                               f"pool of {pool} synthetic inputs", "batch": nb},
+        "kernel_ms": {"forward": round(fwd_ms, 5), "backward": round(bwd_ms, 5)},
+        "roofline": {"bound": "alu", "kernel": "k_mlp_fwd", "achieved": round(fwd_tf, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(fwd_tf / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None},
+        "roofline_kernels": {"backward (3 kernels)": {"bound": "alu", "achieved": round(bwd_tf, 3),
+                                                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                                      "frac": round(bwd_tf / PEAK_FP32_TFLOPS, 4)}},
+        "inference_us_4k_frame": round(inf_us, 2),
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -217,6 +217,60 @@ trs_status trs_batch_frame_arrays(trs_batch batch, void *workspace, int32_t fram
 /* Host: free the batch's device tables (plans stay cached). */
 void trs_batch_destroy(trs_batch batch);
 
+/* ---- Learned per-CTU time predictor (stands in for the previous-frame estimator of
+ * Section 2.1; the paper's conclusion names a better CTU time estimator as future work) ----
+ * A 10 -> 64 -> 64 -> 1 perceptron with exact GELU (0.5 x (1 + erf(x / sqrt 2))), FP32.
+ * Inputs per CTU (raw, before normalisation): texture, variance, mean; the textures of the
+ * left, right, upper and lower neighbours (own value at the frame edge); the previous time;
+ * the mean of the 4 neighbours' previous times (own value at the edge); n / ctu_size^2.
+ * Output: the predicted time in milliseconds.  Weights are row-major [out][in], device. */
+#define TRS_MLP_IN 10
+#define TRS_MLP_HIDDEN 64
+
+typedef struct trs_mlp {
+    const float *w1, *b1, *w2, *b2, *w3, *b3;   /* [64][10], [64], [64][64], [64], [64], [1] */
+} trs_mlp;
+
+typedef struct trs_mlp_grads {
+    float *w1, *b1, *w2, *b2, *w3, *b3;
+} trs_mlp_grads;
+
+/* Input normalisation x' = (x - mean) inv_std, and the training range [lo, hi] per input:
+ * trs_mlp_cost falls back to the plain blend for a CTU with an input outside it. */
+typedef struct trs_mlp_norm {
+    float mean[TRS_MLP_IN], inv_std[TRS_MLP_IN], lo[TRS_MLP_IN], hi[TRS_MLP_IN];
+} trs_mlp_norm;
+
+/* Raw inputs x[c][10] for every CTU from trs_features outputs and the previous times
+ * (device).  Errors: TRS_EINVAL, TRS_EDEVICE. */
+trs_status trs_mlp_inputs(const trs_frame *frame, const uint32_t *tex, const uint32_t *var,
+                          const uint32_t *mean, const uint32_t *prev, float *x,
+                          hipStream_t stream);
+
+/* y[s] for n samples x[s][10] (device); z1, z2 (device [64][n], nullable) keep the hidden
+ * pre-activations for trs_mlp_backward.  Errors: TRS_EINVAL, TRS_EDEVICE. */
+trs_status trs_mlp_forward(const trs_mlp *mlp, const trs_mlp_norm *norm, const float *x,
+                           int64_t n, float *y, float *z1, float *z2, hipStream_t stream);
+
+/* Host: workspace bytes trs_mlp_backward needs for n samples. */
+trs_status trs_mlp_backward_workspace(int64_t n, size_t *bytes);
+
+/* Gradients of sum_s dy[s] y[s] with respect to every weight and bias, written (not
+ * accumulated) to grads; z1, z2 from trs_mlp_forward on the same x.  Summation order is
+ * fixed, so results repeat exactly.  Errors: TRS_EINVAL, TRS_EWORKSPACE, TRS_EDEVICE. */
+trs_status trs_mlp_backward(const trs_mlp *mlp, const trs_mlp_norm *norm, const float *x,
+                            const float *z1, const float *z2, const float *dy, int64_t n,
+                            trs_mlp_grads grads, void *workspace, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* Time map from predictions: cost = rint(1000 y) clamped to [1, 2^31 - 1] where y is finite
+ * and every input lies in [lo, hi]; elsewhere the plain blend of trs_cost_map (tex, prev,
+ * blend), and *n_fallback_dev (nullable) counts those CTUs.  Errors: TRS_EINVAL, TRS_EDEVICE. */
+trs_status trs_mlp_cost(const trs_frame *frame, const float *y, const float *x,
+                        const trs_mlp_norm *norm, const uint32_t *tex, const uint32_t *prev,
+                        trs_blend blend, uint32_t *cost, uint32_t *n_fallback_dev,
+                        hipStream_t stream);
+
 /* Host: |C| and the windows (dtile, drs) the ladder rule picks.  No device work.
  * Errors: TRS_EINVAL. */
 trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params,

@@ -10,3 +10,4 @@ from .binding import (Batch, Partitioner, TrsError, make_frame, make_params, rea
                       trs_search_stats, trs_profile_enable, trs_profile_read,
                       trs_cost_map, trs_decode, trs_features, trs_release_plans, trs_search,
                       trs_search_workspace, trs_space_size)
+from .binding import (trs_mlp_backward, trs_mlp_cost, trs_mlp_forward, trs_mlp_inputs)  # noqa: F401,E402

@@ -68,6 +68,19 @@ class BatchFrame(ctypes.Structure):
                 ("stride_elems", ctypes.c_int64), ("prev", ctypes.c_void_p), ("blend", Blend)]
 
 
+class MLP(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3")]
+
+
+class MLPGrads(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3")]
+
+
+class MLPNorm(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_float * 10), ("inv_std", ctypes.c_float * 10),
+                ("lo", ctypes.c_float * 10), ("hi", ctypes.c_float * 10)]
+
+
 RESULT_BYTES = ctypes.sizeof(Result)
 _lib = None
 
@@ -128,6 +141,19 @@ def lib():
         L.trs_batch_frame_arrays.restype = S
         L.trs_batch_destroy.argtypes = [P]
         L.trs_batch_destroy.restype = None
+        L.trs_mlp_inputs.argtypes = [ctypes.POINTER(Frame), P, P, P, P, P, P]
+        L.trs_mlp_inputs.restype = S
+        L.trs_mlp_forward.argtypes = [ctypes.POINTER(MLP), ctypes.POINTER(MLPNorm), P, ctypes.c_int64,
+                                      P, P, P, P]
+        L.trs_mlp_forward.restype = S
+        L.trs_mlp_backward_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+        L.trs_mlp_backward_workspace.restype = S
+        L.trs_mlp_backward.argtypes = [ctypes.POINTER(MLP), ctypes.POINTER(MLPNorm), P, P, P, P,
+                                       ctypes.c_int64, MLPGrads, P, ctypes.c_size_t, P]
+        L.trs_mlp_backward.restype = S
+        L.trs_mlp_cost.argtypes = [ctypes.POINTER(Frame), P, P, ctypes.POINTER(MLPNorm), P, P, Blend,
+                                   P, P, P]
+        L.trs_mlp_cost.restype = S
         L.trs_strerror.argtypes = [S]
         L.trs_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -412,3 +438,43 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---- learned CTU time predictor ------------------------------------------------------------
+
+def _mlp(ws) -> MLP:
+    return MLP(*(w.data_ptr() for w in ws))
+
+
+def trs_mlp_inputs(frame: Frame, feats: dict, prev, x, stream=None):
+    check(lib().trs_mlp_inputs(ctypes.byref(frame), _ptr(feats["tex"]), _ptr(feats["var"]),
+                               _ptr(feats["mean"]), _ptr(prev), _ptr(x), _stream(stream)), "trs_mlp_inputs")
+    return x
+
+
+def trs_mlp_forward(weights, norm: MLPNorm, x, y, z1=None, z2=None, stream=None):
+    check(lib().trs_mlp_forward(ctypes.byref(_mlp(weights)), ctypes.byref(norm), _ptr(x), x.shape[0], _ptr(y),
+                                None if z1 is None else _ptr(z1), None if z2 is None else _ptr(z2),
+                                _stream(stream)), "trs_mlp_forward")
+    return y
+
+
+def trs_mlp_backward(weights, norm: MLPNorm, x, z1, z2, dy, grads, workspace=None, stream=None):
+    import torch
+    n = x.shape[0]
+    if workspace is None:
+        nb = ctypes.c_size_t()
+        check(lib().trs_mlp_backward_workspace(n, ctypes.byref(nb)), "trs_mlp_backward_workspace")
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+    g = MLPGrads(*(t.data_ptr() for t in grads))
+    check(lib().trs_mlp_backward(ctypes.byref(_mlp(weights)), ctypes.byref(norm), _ptr(x), _ptr(z1), _ptr(z2),
+                                 _ptr(dy), n, g, _ptr(workspace), workspace.numel(), _stream(stream)),
+          "trs_mlp_backward")
+    return grads
+
+
+def trs_mlp_cost(frame: Frame, y, x, norm: MLPNorm, tex, prev, blend: Blend, cost, n_fallback=None, stream=None):
+    check(lib().trs_mlp_cost(ctypes.byref(frame), _ptr(y), _ptr(x), ctypes.byref(norm), _ptr(tex),
+                             None if prev is None else _ptr(prev), blend, _ptr(cost),
+                             None if n_fallback is None else _ptr(n_fallback), _stream(stream)), "trs_mlp_cost")
+    return cost

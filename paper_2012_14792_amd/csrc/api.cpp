@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "space.hpp"
 #include "trs.h"
 
@@ -546,6 +547,68 @@ void trs_batch_destroy(trs_batch batch)
     if (!batch) return;
     if (batch->blob) (void)hipFree(batch->blob);
     delete batch;
+}
+
+static bool mlp_ok(const trs_mlp *m)
+{
+    return m && m->w1 && m->b1 && m->w2 && m->b2 && m->w3 && m->b3;
+}
+
+trs_status trs_mlp_inputs(const trs_frame *frame, const uint32_t *tex, const uint32_t *var,
+                          const uint32_t *mean, const uint32_t *prev, float *x, hipStream_t stream)
+{
+    if (!frame_ok(frame) || !tex || !var || !mean || !prev || !x) return TRS_EINVAL;
+    const int cs = frame->ctu_size;
+    const int W = (frame->width + cs - 1) / cs, H = (frame->height + cs - 1) / cs;
+    return trs::launch_mlp_inputs(W, H, cs, frame->width, frame->height, tex, var, mean, prev, x,
+                                  stream) == hipSuccess ? TRS_OK : TRS_EDEVICE;
+}
+
+trs_status trs_mlp_forward(const trs_mlp *mlp, const trs_mlp_norm *norm, const float *x,
+                           int64_t n, float *y, float *z1, float *z2, hipStream_t stream)
+{
+    if (!mlp_ok(mlp) || !norm || !x || !y || n < 1 || n > (int64_t(1) << 31) || (!z1) != (!z2))
+        return TRS_EINVAL;
+    return trs::launch_mlp_forward(*mlp, *norm, x, n, y, z1, z2, stream) == hipSuccess ? TRS_OK
+                                                                                       : TRS_EDEVICE;
+}
+
+trs_status trs_mlp_backward_workspace(int64_t n, size_t *bytes)
+{
+    if (!bytes || n < 1 || n > (int64_t(1) << 31)) return TRS_EINVAL;
+    *bytes = trs::mlp_backward_workspace(n);
+    return TRS_OK;
+}
+
+trs_status trs_mlp_backward(const trs_mlp *mlp, const trs_mlp_norm *norm, const float *x,
+                            const float *z1, const float *z2, const float *dy, int64_t n,
+                            trs_mlp_grads grads, void *workspace, size_t ws_bytes,
+                            hipStream_t stream)
+{
+    if (!mlp_ok(mlp) || !norm || !x || !z1 || !z2 || !dy || n < 1 || n > (int64_t(1) << 31))
+        return TRS_EINVAL;
+    if (!grads.w1 || !grads.b1 || !grads.w2 || !grads.b2 || !grads.w3 || !grads.b3) return TRS_EINVAL;
+    if (!workspace || ws_bytes < trs::mlp_backward_workspace(n) ||
+        reinterpret_cast<uintptr_t>(workspace) % 256)
+        return TRS_EWORKSPACE;
+    return trs::launch_mlp_backward(*mlp, *norm, x, z1, z2, dy, n, grads,
+                                    static_cast<char *>(workspace), stream) == hipSuccess
+               ? TRS_OK
+               : TRS_EDEVICE;
+}
+
+trs_status trs_mlp_cost(const trs_frame *frame, const float *y, const float *x,
+                        const trs_mlp_norm *norm, const uint32_t *tex, const uint32_t *prev,
+                        trs_blend blend, uint32_t *cost, uint32_t *n_fallback_dev,
+                        hipStream_t stream)
+{
+    if (!frame_ok(frame) || !y || !x || !norm || !tex || !cost || blend.w_prev > 256) return TRS_EINVAL;
+    const int cs = frame->ctu_size;
+    const long long n = (long long)((frame->width + cs - 1) / cs) * ((frame->height + cs - 1) / cs);
+    return trs::launch_mlp_cost(n, y, x, *norm, tex, prev, blend, cost, n_fallback_dev, stream) ==
+                   hipSuccess
+               ? TRS_OK
+               : TRS_EDEVICE;
 }
 
 void trs_release_plans(void)

@@ -173,3 +173,61 @@ def batch_workload(n_frames: int = 512, seed: int = 4, mix=(1, 2, 1)):
 
 def batch_sequence_seed(name: str, seed: int = 4) -> int:
     return seed * 10 + ["fhd", "uhd", "8k"].index(name)
+
+
+class TorchSequenceGenerator:
+    """SequenceGenerator's sequence rendered on a torch device (for bulk training data).
+
+    The random draws are those of SequenceGenerator (same generator, same order); the
+    sinusoid field is evaluated on the device in float64, so frames agree with
+    SequenceGenerator's up to the rounding of that field.
+    """
+
+    def __init__(self, width: int, height: int, seed: int, drift_max: float = 0.0,
+                 device="cuda", n_sin: int = 8, n_blobs: int = 20, base: float = 512.0):
+        import torch
+        self.width, self.height, self.device = int(width), int(height), device
+        rng = np.random.Generator(np.random.PCG64(seed))
+        period = np.exp(rng.uniform(math.log(4.0), math.log(256.0), n_sin))
+        angle = rng.uniform(0.0, math.pi, n_sin)
+        phase = rng.uniform(0.0, 2.0 * math.pi, n_sin)
+        amp = rng.uniform(20.0, 80.0, n_sin)
+        bx = rng.uniform(0.0, width, n_blobs)
+        by = rng.uniform(0.0, height, n_blobs)
+        bsig = rng.uniform(8.0, 200.0, n_blobs)
+        bamp = rng.uniform(50.0, 300.0, n_blobs)
+        bspeed = rng.uniform(0.0, drift_max, n_blobs) if drift_max > 0 else np.zeros(n_blobs)
+        bhead = rng.uniform(0.0, 2.0 * math.pi, n_blobs)
+        self.blobs = []
+        for i in range(n_blobs):
+            rad = int(math.ceil(3.0 * bsig[i]))
+            noise = torch.from_numpy(rng.uniform(-1.0, 1.0, (2 * rad + 1, 2 * rad + 1))).to(device)
+            r = torch.arange(-rad, rad + 1, dtype=torch.float64, device=device)
+            env = torch.exp(-(r[None, :] ** 2 + r[:, None] ** 2) / (2.0 * bsig[i] ** 2))
+            patch = (bamp[i] * env * noise).to(torch.float32)
+            self.blobs.append((bx[i], by[i], bspeed[i] * math.cos(bhead[i]),
+                               bspeed[i] * math.sin(bhead[i]), rad, patch))
+        ys = torch.arange(height, dtype=torch.float64, device=device)[:, None]
+        xs = torch.arange(width, dtype=torch.float64, device=device)[None, :]
+        fld = torch.full((height, width), base, dtype=torch.float64, device=device)
+        for k in range(n_sin):
+            arg = (xs * math.cos(angle[k]) + ys * math.sin(angle[k])) * (2.0 * math.pi / period[k])
+            fld += amp[k] * torch.sin(arg + phase[k])
+        self.base = fld.to(torch.float32)
+
+    def frame(self, f: int = 0):
+        """Frame f as an int16 tensor [height, width] holding 10-bit values."""
+        import torch
+        h, w = self.height, self.width
+        img = self.base.clone()
+        for (bx, by, vx, vy, rad, patch) in self.blobs:
+            cx = int(round(bx + f * vx))
+            cy = int(round(by + f * vy))
+            x0, y0 = cx - rad, cy - rad
+            x1, y1 = cx + rad + 1, cy + rad + 1
+            sx0, sy0 = max(x0, 0), max(y0, 0)
+            sx1, sy1 = min(x1, w), min(y1, h)
+            if sx0 >= sx1 or sy0 >= sy1:
+                continue
+            img[sy0:sy1, sx0:sx1] += patch[sy0 - y0:sy1 - y0, sx0 - x0:sx1 - x0]
+        return torch.clamp(torch.round(img), 0.0, 1023.0).to(torch.int16)
