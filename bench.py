@@ -4,12 +4,20 @@
 Workload: the 4K sequence -- 64 frames of 3840x2160 10-bit luma (30 x 17 CTUs of 128),
 N = 8 slices/threads, tile grids up to 6 x 4, up to 4 slices per tile, lambda = 1/10, the
 ladder rule's (3, 1) window: 5,914,718 candidates per frame.  One step = every frame of
-the sequence through features -> predicted time map -> two-step exhaustive search, one frame
-per launch sequence, inputs (luma and previous-frame CTU times) resident in HBM.
+the sequence through features -> predicted time map -> two-step exhaustive search, inputs
+(luma and previous-frame CTU times) resident in HBM.  The step runs in one of two forms,
+both timed, both checked against each other:
 
-Prints one JSON line: frames/s (4K frames partitioned per second) with candidates scored
-per second, the dominant kernel's roofline fraction (HIP events around it, on its stream),
-and the CPU oracle timed on a bounded sample of the same workload on the host's cores.
+  batched  one trs_batch_run over all frames (six launches, persistent search kernels)
+  streams  one trs_partition launch sequence per frame, frames spread over 8 streams
+
+Prints one JSON line: frames/s (4K frames partitioned per second) of the chosen form
+(default batched) with candidates scored per second, the dominant kernel's roofline
+fraction (HIP events around it, on its stream), and the CPU oracle timed on a bounded
+sample of the same workload on the host's cores.
+
+Other workloads: --workload batch512 (512 mixed 1080p/4K/8K frames with mixed N) and
+--workload mlp (training steps of the learned CTU-time predictor).
 """
 from __future__ import annotations
 
@@ -41,7 +49,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=64)
-    ap.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0: 2 x cores)")
+    ap.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0: 4 x cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16, help="oracle worker threads (cap)")
     ap.add_argument("--sched-block", type=int, default=0)
@@ -51,6 +59,9 @@ def main():
                     help="uhd_seq: the 64-frame 4K sequence; batch512: 512 mixed frames in one batch; "
                          "mlp: training steps of the learned CTU-time predictor")
     ap.add_argument("--mlp-batch", type=int, default=65536)
+    ap.add_argument("--form", default="batched", choices=["batched", "streams"],
+                    help="4K sequence: one batched launch sequence per step, or per-frame launches "
+                         "over --streams streams")
     ap.add_argument("--batch-frames", type=int, default=512)
     ap.add_argument("--wgs-per-cu", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -116,15 +127,16 @@ def main():
         del src, dst
         log("copy probe: 1 GiB device-to-device copy done")
 
-    # frames are independent: S streams (default priority) each run whole frames, so the
-    # kernels of up to S frames overlap; each stream owns its buffers and workspace
+    # ---- form 1: per-frame launch sequences over S streams (default priority) --------------
+    # frames are independent: each stream runs whole frames with its own buffers, so the
+    # kernels of up to S frames overlap
     S = max(1, args.streams)
     parts = [B.Partitioner(w, h, params) for _ in range(S)]
     part = parts[0]
     outs = torch.empty((F, B.RESULT_BYTES), dtype=torch.uint8, device="cuda")
     streams = [torch.cuda.Stream() for _ in range(S)]
 
-    def step():
+    def step_streams():
         base = torch.cuda.current_stream()
         for st in streams:
             st.wait_stream(base)
@@ -135,62 +147,74 @@ def main():
         for st in streams:
             base.wait_stream(st)
 
-    # warm up eagerly (builds and uploads the plan), then capture one step in a HIP graph
     for _ in range(max(args.warmup, 1)):
-        step()
+        step_streams()
     torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    cap = torch.cuda.Stream()
-    cap.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(cap):
-        with torch.cuda.graph(graph, stream=cap):
-            step()
-    torch.cuda.current_stream().wait_stream(cap)
-    for _ in range(args.warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps), step captured as a graph of {F} frames on {S} streams")
+    g_streams = capture(step_streams)
 
-    # ---- timed region: K graph replays, one per step ---------------------------------------
+    # ---- form 2: the batched form, every frame in one six-launch sequence --------------------
+    tuned = (autotune.load(f"{autotune.arch()}|uhd_seq{F}") or {}) if not args.sched_block else {}
+    block = args.sched_block or tuned.get("block", 0)
+    wgs = args.wgs_per_cu or tuned.get("wgs_per_cu", 0)
+    batch = B.Batch([dict(width=w, height=h, params=params, luma=luma[f], prev=prev[f]) for f in range(F)],
+                    block=block, wgs_per_cu=wgs)
+    for _ in range(max(args.warmup, 1)):
+        batch.enqueue()
     torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        graph.replay()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    fps = F * args.steps / elapsed
-    log(f"timed {args.steps} graph replays in {elapsed:.3f} s: {fps:.1f} frames/s")
-    graph_outs = outs.clone()
+    g_batch = batch.capture()
 
-    # ---- eager steps with HIP events around each kernel of interest ------------------------
-    # (events on the stream the kernels run on: torch's current stream)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(F)]
+    fps_streams, el_streams = time_graph(g_streams, args.warmup, args.steps, F)
+    outs_streams = outs.clone()
+    fps_batch, el_batch = time_graph(g_batch, args.warmup, args.steps, F)
+    outs_batch = batch.out.clone()
+    log(f"per-frame launches over {S} streams: {fps_streams:.1f} frames/s; batched: {fps_batch:.1f} frames/s")
+    batched = args.form == "batched"
+    fps, elapsed = (fps_batch, el_batch) if batched else (fps_streams, el_streams)
+    graph_outs = outs_batch if batched else outs_streams
+    forms_equal = bool(torch.equal(outs_batch, outs_streams))
+
+    # ---- eager runs of the reported form with HIP events around its kernels ----------------
+    # (events on the stream the kernels are launched on: torch's current stream)
     B.trs_profile_enable(True)
-    feat_ms = 0.0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for f in range(F):
-            ev[f][0].record()
-            B.trs_features(frame, luma[f], part.feats)
-            ev[f][1].record()
-            B.trs_cost_map(frame, part.feats["tex"], prev[f], part.blend, part.cost, part.flags)
-            B.trs_search(frame, params, part.cost, part.feats["s1"], part.feats["s2"], part.ws, outs[f])
+    if batched:
+        for _ in range(args.steps):
+            batch.enqueue()
         torch.cuda.synchronize()
-        feat_ms += sum(a.elapsed_time(b) for a, b in ev)
-    eager_elapsed = time.perf_counter() - t0
-    B.trs_profile_enable(False)
-    ms1, ms2, n_search = B.trs_profile_read()
-    n_launch = F * args.steps
-    avg_feat, avg1, avg2 = feat_ms / n_launch, ms1 / max(n_search, 1), ms2 / max(n_search, 1)
-    eager_equals_graph = bool(torch.equal(outs, graph_outs))
+        eager_elapsed = time.perf_counter() - t0
+        B.trs_profile_enable(False)
+        stage_ms, runs = B.trs_profile_read_batch()
+        kms = {k: v / max(runs, 1) for k, v in stage_ms.items()}
+        eager_out = batch.out
+        launch_frames = F
+    else:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(F)]
+        feat_ms = 0.0
+        for _ in range(args.steps):
+            for f in range(F):
+                ev[f][0].record()
+                B.trs_features(frame, luma[f], part.feats)
+                ev[f][1].record()
+                B.trs_cost_map(frame, part.feats["tex"], prev[f], part.blend, part.cost, part.flags)
+                B.trs_search(frame, params, part.cost, part.feats["s1"], part.feats["s2"], part.ws, outs[f])
+            torch.cuda.synchronize()
+            feat_ms += sum(a.elapsed_time(b) for a, b in ev)
+        eager_elapsed = time.perf_counter() - t0
+        B.trs_profile_enable(False)
+        ms1, ms2, n_search = B.trs_profile_read()
+        n = F * args.steps
+        kms = {"features": feat_ms / n, "step1": ms1 / max(n_search, 1), "step2": ms2 / max(n_search, 1)}
+        eager_out = outs
+        launch_frames = 1
+    eager_equals_graph = bool(torch.equal(eager_out, graph_outs))
     res_all = [B.result_dict(B.Result.from_buffer_copy(bytes(graph_outs[f].cpu().numpy().tobytes())))
                for f in range(F)]
     step2_frac = sum(r["n_step2"] for r in res_all) / max(1, sum(r["n_feasible"] for r in res_all))
-    log(f"eager: {n_launch / eager_elapsed:.1f} frames/s; kernel ms features {avg_feat:.4f} "
-        f"step1 {avg1:.4f} step2 {avg2:.4f}")
+    log(f"eager {args.form}: {F * args.steps / eager_elapsed:.1f} frames/s; kernel ms "
+        + " ".join(f"{k} {v:.4f}" for k, v in kms.items()))
 
     # ---- roofline of each measured kernel; the longest one is reported as dominant ---------
-    # features: HBM bytes per launch = every luma sample once + the per-CTU outputs
+    # features: HBM bytes per frame = every luma sample once + the per-CTU outputs
     feat_bytes = 2 * w * h + W * H * (5 * 4 + 8)
     # step 1: per feasible candidate one 64-bit max per tile (3 lane-ops) and a 64-bit
     # minimum (3); per record slice one rectangle sum and max (10)
@@ -199,13 +223,18 @@ def main():
     # max and add (5); per candidate the bound test and key compare (6); per record slice
     # three rectangle sums, the exact floor(S1^2 / n) and the sums (40)
     ops2 = step2_frac * (5 * stats["tile_lookups"] + 6 * stats["feasible"] + 40 * stats["record_slices"])
+    pre = "k_search_batch" if batched else "k_search"
+    kblock = (block or 256) if batched else (params.sched_block or 256)
+    fk = "k_features_batch<128>" if batched else "k_features<128>"
     kernels = {
-        "k_features<128>": {"bound": "hbm", "avg_ms": avg_feat, "work": feat_bytes, "peak": PEAK_HBM_GBS,
-                            "unit": "GB/s", "scale": 1e9},
-        "k_search<256, false> (step 1)": {"bound": "alu", "avg_ms": avg1, "work": ops1,
-                                          "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
-        "k_search<256, true> (step 2)": {"bound": "alu", "avg_ms": avg2, "work": ops2,
-                                         "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
+        fk: {"bound": "hbm", "avg_ms": kms["features"], "work": feat_bytes * launch_frames,
+             "peak": PEAK_HBM_GBS, "unit": "GB/s", "scale": 1e9},
+        (f"k_step1_units<{kblock}> (step 1)" if batched else f"k_search<{kblock}, false> (step 1)"): {
+            "bound": "alu", "avg_ms": kms["step1"], "work": ops1 * launch_frames,
+            "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
+        f"{pre}<{kblock}, true> (step 2)": {
+            "bound": "alu", "avg_ms": kms["step2"], "work": ops2 * launch_frames,
+            "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
     }
     table = {}
     for name, k in kernels.items():
@@ -224,7 +253,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         cores = min(len(os.sched_getaffinity(0)), args.cpu_threads)
-        n_cpu = min(F, args.cpu_frames or 2 * cores)
+        n_cpu = min(F, args.cpu_frames or 4 * cores)
         oparams = oracle.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
                                      cfg["max_rs_per_tile"], lam=cfg["lam"])
         otex = [oracle.features(frames[f])["tex"] for f in range(n_cpu)]
@@ -237,7 +266,7 @@ def main():
         cpu = {"value": round(n_cpu / wall, 4), "unit": "4K frames/s", "cores": cores, "kind": "oracle",
                "sample": f"frames 0..{n_cpu - 1} of the same 64-frame 4K sequence, whole path "
                          f"(features, time map, two-step search), one frame per thread, "
-                         f"{wall:.1f} s wall"}
+                         f"{wall:.1f} s wall ({wall * cores:.0f} thread-seconds)"}
         ok = 0
         for f in range(n_cpu):
             g = res_all[f]
@@ -245,7 +274,8 @@ def main():
             same = all(g[k] == r[k] for k in ("rank", "t_min", "t_sel", "q_sel", "n_feasible", "rs_time")) \
                 and [tuple(x) for x in g["rs"]] == [tuple(x) for x in r["rs"]]
             ok += same
-        parity = f"{ok}/{n_cpu} graph-replayed frames bit-exact vs oracle; eager == graph: {eager_equals_graph}"
+        parity = (f"{ok}/{n_cpu} graph-replayed frames bit-exact vs oracle; eager == graph: {eager_equals_graph}; "
+                  f"batched == per-frame on {F} frames: {forms_equal}")
         log(parity)
 
     res = {
@@ -264,17 +294,19 @@ def main():
         "config": {"workload": f"4K sequence: {F} frames 3840x2160 10-bit, CTU 128 (30x17), "
                                f"N=8 slices, tiles <= 6x4, <= 4 slices/tile, lambda=1/10, "
                                f"window ({stats['dtile']},{stats['drs']}), "
-                               f"{stats['candidates']} candidates/frame ({stats['feasible']} area-feasible), "
-                               f"one frame per launch sequence",
+                               f"{stats['candidates']} candidates/frame ({stats['feasible']} area-feasible)",
                    "frames": F, "width": w, "height": h, "n_threads": 8,
                    "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
-                   "sched_block": params.sched_block or 256, "sched_item": params.sched_item or 512,
-                   "streams": S,
-                   "timing": f"HIP graph of one step ({F} trs_partition calls over {S} streams), replayed K times"},
+                   "form": args.form,
+                   "timing": (f"HIP graph of one step (one trs_batch_run over the {F} frames), replayed K times"
+                              if batched else
+                              f"HIP graph of one step ({F} trs_partition calls over {S} streams), replayed K times")},
         "candidates_scored_per_s": round(fps * stats["candidates"], 1),
         "feasible_scored_per_s": round(fps * stats["feasible"], 1),
-        "eager_value": round(n_launch / eager_elapsed, 3),
-        "kernel_ms": {"features": round(avg_feat, 5), "step1": round(avg1, 5), "step2": round(avg2, 5)},
+        "batched_value": round(fps_batch, 3),
+        "per_frame_streams_value": round(fps_streams, 3),
+        "eager_value": round(F * args.steps / eager_elapsed, 3),
+        "kernel_ms": {k: round(v, 5) for k, v in kms.items()},
         "step2_fraction": round(step2_frac, 4),
         "roofline": roofline,
         "roofline_kernels": table,
@@ -282,6 +314,33 @@ def main():
         "parity": parity,
     }
     print(json.dumps(res), flush=True)
+
+
+def capture(fn):
+    """A HIP graph of one call of fn (captured on a side stream)."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap):
+            fn()
+    torch.cuda.current_stream().wait_stream(cap)
+    return g
+
+
+def time_graph(g, warmup, steps, frames_per_step):
+    """K replays bracketed by device synchronisation; returns (frames/s, seconds)."""
+    import torch
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return frames_per_step * steps / el, el
 
 
 def run_batch(args):

@@ -282,10 +282,11 @@ trs_status trs_space_size(const trs_frame *frame, const trs_search_params *param
  * only these); tile_lookups = sum over feasible candidates of their tile count; items =
  * work items (one work-group each); records / record_slices = tile-option records built per
  * step and the slices they sum; records_max = largest record count of one item;
- * table_bytes = size of the device tables.  Errors: as trs_search_workspace. */
+ * entries_max = largest (candidates x tiles) of one item, rounded up to 8; table_bytes =
+ * size of the device tables.  Errors: as trs_search_workspace. */
 typedef struct trs_plan_stats {
     int64_t candidates, feasible, tile_lookups, items, records, record_slices, table_bytes;
-    int32_t dtile, drs, records_max, pad;
+    int32_t dtile, drs, records_max, entries_max;
 } trs_plan_stats;
 
 trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *params,
@@ -299,12 +300,16 @@ trs_status trs_decode(const trs_frame *frame, const trs_search_params *params, i
                       trs_result *out_host);
 
 /* Kernel timing.  While enabled (on != 0), every trs_search records HIP events on its
- * stream around its step-1 kernel and around its step-2 kernel.  trs_profile_read
- * waits for the recorded events, returns the summed milliseconds of the step-1 and step-2
- * kernels and the number of searches timed, and clears the record.  Host only; returns
- * TRS_EDEVICE if an event call fails. */
+ * stream around its step-1 kernel and around its step-2 kernel, and every trs_batch_run
+ * records events between its six launches.  trs_profile_read waits for the recorded search
+ * events, returns the summed milliseconds of the step-1 and step-2 kernels and the number of
+ * searches timed, and clears that record.  trs_profile_read_batch does the same for batch
+ * runs: ms[0..5] = features, cost map + prefix sums, step 1, T~min, step 2, result.  Enabling
+ * is for eager (not graph-captured) launches.  Host only; returns TRS_EDEVICE if an event
+ * call fails. */
 void trs_profile_enable(int on);
 trs_status trs_profile_read(double *ms_step1, double *ms_step2, int64_t *searches);
+trs_status trs_profile_read_batch(double *ms, int64_t *runs);
 
 /* Host: drop every cached candidate-space plan and free its device tables.  Batches created
  * before this call must be destroyed, not run, afterwards. */

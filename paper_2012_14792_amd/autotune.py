@@ -9,6 +9,7 @@ candidates step 2 scored, which depends on how the space is cut into work items.
 Results are cached as JSON keyed by GPU architecture, frame geometry and search parameters:
 
     python -m paper_2012_14792_amd.autotune --workload uhd_seq
+    python -m paper_2012_14792_amd.autotune --workload uhd_batch
     python -m paper_2012_14792_amd.autotune --workload batch512
 
 `load(key)` returns a cached schedule (or None); `tuned_params(...)` fills one in.
@@ -171,7 +172,7 @@ def tune_batch(items, reps=10, candidates=BATCH_CANDIDATES, log=print) -> dict:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["uhd_seq", "batch512", "all"], default="all")
+    ap.add_argument("--workload", choices=["uhd_seq", "uhd_batch", "batch512", "all"], default="all")
     ap.add_argument("--frames", type=int, default=32)
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
@@ -202,6 +203,22 @@ def main(argv=None):
                 store(frame_key(w, h, p), {"sched_block": res["best"]["sched_block"],
                                            "sched_item": res["best"]["sched_item"]})
                 report[f"{name}_N{N}"] = res
+    if args.workload in ("uhd_batch", "all"):
+        # the batched form over the 64-frame 4K sequence
+        cfg = synth.CONFIGS["uhd_n8"]
+        w, h = cfg["width"], cfg["height"]
+        gen = synth.SequenceGenerator(w, h, cfg["seed"], cfg["drift"])
+        W, H = synth.ctu_grid(w, h)
+        rng = np.random.default_rng(0)
+        p = tuned_params(w, h, B.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
+                                             cfg["max_rs_per_tile"], lam=cfg["lam"]))
+        items = [dict(width=w, height=h, params=p, luma=torch.from_numpy(gen.frame(f).view(np.int16)).cuda(),
+                      prev=torch.from_numpy(rng.integers(200, 3000, W * H).astype(np.int32)).cuda())
+                 for f in range(64)]
+        log("uhd_seq64 batched:")
+        res = tune_batch(items, log=log)
+        store(f"{arch()}|uhd_seq64", {"block": res["best"]["block"], "wgs_per_cu": res["best"]["wgs_per_cu"]})
+        report["uhd_seq64"] = res
     if args.workload in ("batch512", "all"):
         spec = synth.batch_workload(512)
         gens = {n: synth.SequenceGenerator(*synth.SIZES[n], synth.batch_sequence_seed(n), 8.0)

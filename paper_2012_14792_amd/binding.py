@@ -47,7 +47,7 @@ class PlanStats(ctypes.Structure):
                 ("tile_lookups", ctypes.c_int64), ("items", ctypes.c_int64),
                 ("records", ctypes.c_int64), ("record_slices", ctypes.c_int64),
                 ("table_bytes", ctypes.c_int64), ("dtile", ctypes.c_int32), ("drs", ctypes.c_int32),
-                ("records_max", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("records_max", ctypes.c_int32), ("entries_max", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -129,6 +129,8 @@ def lib():
         L.trs_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
         L.trs_profile_read.restype = S
+        L.trs_profile_read_batch.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.trs_profile_read_batch.restype = S
         L.trs_batch_create.argtypes = [ctypes.POINTER(BatchFrame), ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
         L.trs_batch_create.restype = S
@@ -222,6 +224,17 @@ def trs_profile_read() -> tuple[float, float, int]:
     a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     check(lib().trs_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)), "trs_profile_read")
     return a.value, b.value, n.value
+
+
+BATCH_STAGES = ("features", "cost_sat", "step1", "tmin", "step2", "final")
+
+
+def trs_profile_read_batch() -> tuple[dict, int]:
+    """Summed milliseconds per batch launch stage since the last read, and the run count."""
+    ms = (ctypes.c_double * 6)()
+    n = ctypes.c_int64()
+    check(lib().trs_profile_read_batch(ms, ctypes.byref(n)), "trs_profile_read_batch")
+    return dict(zip(BATCH_STAGES, list(ms))), n.value
 
 
 def trs_release_plans() -> None:

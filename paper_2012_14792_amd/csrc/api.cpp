@@ -46,6 +46,7 @@ thread_local FastPlan t_fast;
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<std::array<hipEvent_t, 4>> g_prof_events;
+std::vector<std::array<hipEvent_t, 7>> g_prof_batch;
 
 PlanKey plan_key(const trs_frame *f, const trs_search_params *p)
 {
@@ -150,6 +151,7 @@ trs_status device_view(PlanEntry &e, trs::SpaceView *view)
     v.n_shapes = (int32_t)pl.shapes.size();
     v.n_unif = pl.n_unif;
     v.rec_max = pl.rec_max;
+    v.rid_max = pl.rid_max;
     v.n_feasible = pl.n_feasible;
     v.cu = pl.cu;
     v.ru = pl.ru;
@@ -354,6 +356,27 @@ trs_status trs_profile_read(double *ms_step1, double *ms_step2, int64_t *searche
     return st;
 }
 
+trs_status trs_profile_read_batch(double *ms, int64_t *runs)
+{
+    if (!ms || !runs) return TRS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    trs_status st = TRS_OK;
+    for (int k = 0; k < 6; k++) ms[k] = 0.0;
+    for (auto &ev : g_prof_batch) {
+        if (hipEventSynchronize(ev[6]) != hipSuccess) st = TRS_EDEVICE;
+        for (int k = 0; k < 6; k++) {
+            float x = 0;
+            if (hipEventElapsedTime(&x, ev[k], ev[k + 1]) != hipSuccess) st = TRS_EDEVICE;
+            ms[k] += x;
+        }
+    }
+    *runs = (int64_t)g_prof_batch.size();
+    for (auto &ev : g_prof_batch)
+        for (auto &x : ev) (void)hipEventDestroy(x);
+    g_prof_batch.clear();
+    return st;
+}
+
 trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *params,
                             trs_plan_stats *out)
 {
@@ -377,6 +400,7 @@ trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *par
     out->dtile = pl.dt;
     out->drs = pl.dr;
     out->records_max = pl.rec_max;
+    out->entries_max = pl.rid_max;
     return TRS_OK;
 }
 
@@ -408,7 +432,7 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     std::vector<const PlanEntry *> plan_of_view;
     std::vector<int> ctu_frame, item_frame;
     long long off = 0;
-    int rec_max = 0;
+    int rec_max = 0, rid_max = 0;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         for (int f = 0; f < n_frames; f++) {
@@ -436,6 +460,7 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
                 plan_of_view.push_back(e);
             }
             rec_max = std::max(rec_max, v.rec_max);
+            rid_max = std::max(rid_max, v.rid_max);
             trs::BatchFrameDev fd{};
             fd.luma = bf.luma;
             fd.stride = bf.stride_elems;
@@ -466,14 +491,41 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     auto up = [](long long v) { return (v + 255) & ~255ll; };
     b->launch.o_item_min = up(off);
     b->launch.o_part = b->launch.o_item_min + up(8 * total_items);
-    b->ws_bytes = (size_t)(b->launch.o_part + up((long long)sizeof(trs::Partial) * total_items));
-    // device copy of views, frames and the two index lists
+    b->launch.o_live = b->launch.o_part + up((long long)sizeof(trs::Partial) * total_items);
+    b->launch.o_live_n = b->launch.o_live + up(4 * total_items);
+    b->ws_bytes = (size_t)(b->launch.o_live_n + 256);
+    // frame-inner step-1 units: frames grouped by plan into chunks of kChunk, units ordered
+    // item-major so one work-group's range revisits an item's tables chunk after chunk
+    std::vector<trs::UnitDev> units;
+    std::vector<int> chunk_frames;
+    const bool use_units = trs::unit_lds_bytes(rec_max, rid_max) > 0;
+    if (use_units) {
+        for (int p = 0; p < (int)views.size(); p++) {
+            std::vector<int> fl;
+            for (int f = 0; f < n_frames; f++)
+                if (b->frames[f].plan == p) fl.push_back(f);
+            const int c0 = (int)(chunk_frames.size() / trs::kChunk);
+            const int nc = ((int)fl.size() + trs::kChunk - 1) / trs::kChunk;
+            for (int c = 0; c < nc; c++)
+                for (int j = 0; j < trs::kChunk; j++) {
+                    const int q = c * trs::kChunk + j;
+                    chunk_frames.push_back(q < (int)fl.size() ? fl[q] : -1);
+                }
+            const int n_items = (int)plan_of_view[p]->plan->items.size();
+            for (int i = 0; i < n_items; i++)
+                for (int c = 0; c < nc; c++) units.push_back(trs::UnitDev{p, i, c0 + c, 0});
+        }
+        if (units.size() > (size_t)INT32_MAX / 2) return TRS_ENOSPACE;
+    }
+    // device copy of views, frames and the index lists
     std::vector<std::tuple<const void *, size_t, size_t>> parts;
     size_t boff = 0;
     size_t o_views = add_array(parts, boff, views);
     size_t o_frames = add_array(parts, boff, b->frames);
     size_t o_cf = add_array(parts, boff, ctu_frame);
     size_t o_if = add_array(parts, boff, item_frame);
+    size_t o_units = add_array(parts, boff, units);
+    size_t o_chf = add_array(parts, boff, chunk_frames);
     const size_t bytes = (boff + 255) & ~size_t(255);
     std::vector<char> host(bytes, 0);
     for (auto &pt : parts)
@@ -489,12 +541,16 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     L.frames = reinterpret_cast<const trs::BatchFrameDev *>(bp + o_frames);
     L.ctu_frame = reinterpret_cast<const int *>(bp + o_cf);
     L.item_frame = reinterpret_cast<const int *>(bp + o_if);
+    L.units = use_units ? reinterpret_cast<const trs::UnitDev *>(bp + o_units) : nullptr;
+    L.chunk_frames = use_units ? reinterpret_cast<const int *>(bp + o_chf) : nullptr;
+    L.n_units = (int)units.size();
     L.n_frames = n_frames;
     L.total_ctus = (int)ctu_frame.size();
     L.total_items = (int)total_items;
     L.cs = cs;
     L.block = block ? block : 256;
     L.rec_max = rec_max;
+    L.rid_max = rid_max;
     int n_cu = 0;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
         n_cu = 256;
@@ -502,6 +558,10 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     const int occ2 = wgs_per_cu ? wgs_per_cu : trs::batch_occupancy(L.block, rec_max, true);
     L.grid1 = (int)std::max<long long>(1, std::min<long long>(total_items, (long long)n_cu * occ1));
     L.grid2 = (int)std::max<long long>(1, std::min<long long>(total_items, (long long)n_cu * occ2));
+    if (use_units) {
+        const int occu = wgs_per_cu ? wgs_per_cu : trs::unit_occupancy(L.block, rec_max, rid_max);
+        L.grid_u = (int)std::max<long long>(1, std::min<long long>(L.n_units, (long long)n_cu * occu));
+    }
     *out = b.release();
     return TRS_OK;
 }
@@ -519,7 +579,19 @@ trs_status trs_batch_run(trs_batch batch, void *workspace, size_t ws_bytes, trs_
     if (!batch || !out_dev) return TRS_EINVAL;
     if (!workspace || ws_bytes < batch->ws_bytes || reinterpret_cast<uintptr_t>(workspace) % 256)
         return TRS_EWORKSPACE;
-    return trs::launch_batch(batch->launch, static_cast<char *>(workspace), out_dev, stream) == hipSuccess
+    std::array<hipEvent_t, 7> ev{};
+    bool prof = false;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (g_prof_on) {
+            for (auto &x : ev)
+                if (hipEventCreate(&x) != hipSuccess) return TRS_EDEVICE;
+            g_prof_batch.push_back(ev);
+            prof = true;
+        }
+    }
+    return trs::launch_batch(batch->launch, static_cast<char *>(workspace), out_dev, stream,
+                             prof ? ev.data() : nullptr) == hipSuccess
                ? TRS_OK
                : TRS_EDEVICE;
 }

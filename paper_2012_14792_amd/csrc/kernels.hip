@@ -55,6 +55,7 @@ __device__ __forceinline__ long long wave_incl_scan(long long v, int lane)
 __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ u16x2 as_u16x2(uint32_t w) { return __builtin_bit_cast(u16x2, w); }
 
 // ---------------------------------------------------------------------------------------
@@ -924,13 +925,15 @@ k_features_batch(const BatchFrameDev *__restrict__ frames, const int *__restrict
                      reinterpret_cast<uint32_t *>(ws + fr.o_var));
 }
 
-// One work-group per frame: cost map (overflow flag in the frame's header) and SATs.
+// One work-group per frame: cost map (overflow flag in the frame's header) and SATs.  The
+// first work-group also clears the step-2 list length.
 __global__ void __launch_bounds__(256)
-k_cost_sat_batch(const BatchFrameDev *__restrict__ frames, char *ws)
+k_cost_sat_batch(const BatchFrameDev *__restrict__ frames, char *ws, int *live_n)
 {
     const BatchFrameDev fr = frames[blockIdx.x];
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws + fr.o_hdr);
     if (threadIdx.x == 0) hdr->pad0 = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *live_n = 0;
     __syncthreads();
     cost_sat_body(fr.W, fr.H, reinterpret_cast<const uint32_t *>(ws + fr.o_tex), fr.prev, fr.a,
                   fr.b, fr.wp, reinterpret_cast<uint32_t *>(ws + fr.o_cost),
@@ -945,21 +948,27 @@ k_cost_sat_batch(const BatchFrameDev *__restrict__ frames, char *ws)
 // Persistent search over every (frame, item) of the batch: work-group b takes a contiguous
 // range of the flat item list (ranges of neighbouring b stay on one XCD).  Step 2 skips
 // items whose step-1 minimum exceeds their frame's Eq. 4 bound.
+//
+// Step 1 (P2 false) walks the flat (frame, item) list; step 2 walks the list of live entries
+// k_tmin_batch compacted, so its work spreads evenly over the grid.
 template <int BS, bool P2>
 __global__ void __launch_bounds__(BS)
 k_search_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restrict__ frames,
-               const int *__restrict__ item_frame, int total, char *ws,
-               unsigned long long *__restrict__ item_min, Partial *__restrict__ part, int rec_max)
+               const int *__restrict__ item_frame, int n_flat, char *ws,
+               unsigned long long *__restrict__ item_min, Partial *__restrict__ part, int rec_max,
+               const int *__restrict__ live, const int *__restrict__ live_n)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds);
     unsigned long long *recQ = recT + rec_max;
     const int tid = threadIdx.x;
     const int G = gridDim.x, b = xcd_item(blockIdx.x, G);
+    const int total = P2 ? *live_n : n_flat;
     const int beg = (int)((long long)total * b / G), end = (int)((long long)total * (b + 1) / G);
     int cur = -1;
     BatchFrameDev fr{};
-    for (int g = beg; g < end; g++) {
+    for (int x = beg; x < end; x++) {
+        const int g = P2 ? live[x] : x;
         const int f = item_frame[g];
         if (f != cur) {
             fr = frames[f];
@@ -967,14 +976,7 @@ k_search_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restr
         }
         const SpaceView &sp = plans[fr.plan];
         const int i = g - fr.item_base;
-        unsigned long long bound = kNone;
-        if (P2) {
-            bound = reinterpret_cast<const WsHeader *>(ws + fr.o_hdr)->bound;
-            if (item_min[g] > bound) {
-                if (tid == 0) part[g] = Partial{kNone, kNone, LLONG_MAX, i, -1, 0, 0};
-                continue;
-            }
-        }
+        const unsigned long long bound = P2 ? reinterpret_cast<const WsHeader *>(ws + fr.o_hdr)->bound : kNone;
         const ItemDev it = sp.items[i];
         __syncthreads();                             // the previous item's records are read
         unsigned long long tb;
@@ -990,31 +992,209 @@ k_search_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restr
     }
 }
 
-// One work-group per frame: T~min and the Eq. 4 bound from the frame's item minima.
+// One work-group per frame: T~min and the Eq. 4 bound from the frame's item minima; the
+// frame's items within the bound are appended (in item order, at a position reserved with
+// one atomic) to the step-2 list, and the others get an empty partial.
 __global__ void __launch_bounds__(256)
 k_tmin_batch(const BatchFrameDev *__restrict__ frames,
-             const unsigned long long *__restrict__ item_min, char *ws)
+             const unsigned long long *__restrict__ item_min, char *ws,
+             Partial *__restrict__ part, int *__restrict__ live, int *__restrict__ live_n)
 {
     constexpr int NW = 256 / kWave;
     __shared__ unsigned long long rt[NW];
+    __shared__ unsigned long long sbound;
+    __shared__ int wcnt[NW];
+    __shared__ int sbase;
     const BatchFrameDev fr = frames[blockIdx.x];
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const unsigned long long *im = item_min + fr.item_base;
     unsigned long long t = kNone;
-    for (int i = tid; i < fr.n_items; i += 256) t = min(t, item_min[fr.item_base + i]);
+    int cnt = 0;
+    for (int i = tid; i < fr.n_items; i += 256) t = min(t, im[i]);
 #pragma unroll
     for (int m = kWave / 2; m >= 1; m >>= 1) t = min(t, shfl_xor64(t, m));
     if (lane == 0) rt[wv] = t;
     __syncthreads();
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(ws + fr.o_hdr);
     if (tid == 0) {
         unsigned long long tmin = kNone;
         for (int i = 0; i < NW; i++) tmin = min(tmin, rt[i]);
         unsigned long long bnd = kNone;
         if (fr.lam_num >= 0 && tmin != kNone)
             bnd = tmin * (unsigned long long)(fr.lam_den + fr.lam_num) / (unsigned long long)fr.lam_den;
-        WsHeader *hdr = reinterpret_cast<WsHeader *>(ws + fr.o_hdr);
         hdr->tmin = tmin;
         hdr->bound = bnd;
-        hdr->n_live = fr.n_items;
+        sbound = bnd;
+    }
+    __syncthreads();
+    const unsigned long long bound = sbound;
+    for (int i = tid; i < fr.n_items; i += 256) cnt += im[i] <= bound;
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, kWave);
+    if (lane == 0) wcnt[wv] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+        for (int i = 0; i < NW; i++) n += wcnt[i];
+        hdr->n_live = n;
+        sbase = n ? atomicAdd(live_n, n) : 0;
+    }
+    __syncthreads();
+    int base = sbase;
+    for (int i0 = 0; i0 < fr.n_items; i0 += 256) {
+        const int i = i0 + tid;
+        const bool in = i < fr.n_items;
+        const bool ok = in && im[i] <= bound;
+        if (in && !ok) part[fr.item_base + i] = Partial{kNone, kNone, LLONG_MAX, i, -1, 0, 0};
+        const unsigned long long mask = __ballot(ok);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        __syncthreads();                               // wcnt of the previous chunk is read
+        if (lane == 0) wcnt[wv] = __popcll(mask);
+        __syncthreads();
+        int off = base;
+        for (int q = 0; q < wv; q++) off += wcnt[q];
+        if (ok) live[off + before] = fr.item_base + i;
+        for (int q = 0; q < NW; q++) base += wcnt[q];
+    }
+}
+
+// Frame-inner step 1 for a chunk of up to kChunk frames that share one plan: the item's
+// records are built for every frame of the chunk into LDS as [record][frame] (a padded row
+// per record), then each lane takes candidates, reads each tile's record index once and
+// updates all frames' running maxima from that row.  Writes item_min for each frame.
+constexpr int kRecRow = kChunk + 2;                     // u64 per record row (16-byte rows)
+
+// Pointers read from device tables are generic; these views tell the compiler they address
+// global memory, so loads through them are global (not flat) loads.
+template <class T> using gptr = const __attribute__((address_space(1))) T *;
+template <class T> __device__ __forceinline__ gptr<T> as_global(const T *p) { return (gptr<T>)p; }
+
+// Minimum over the work-group's wave of each of kChunk values per lane, reduce-scattered:
+// after the three halving exchanges lane l holds the partial of value (l >> 3) & 7 over 8
+// lanes, and three more exchanges finish it.  Returns that value's wave minimum (valid in
+// lanes with l % 8 == 0).
+__device__ __forceinline__ unsigned long long wave_min8(const unsigned long long (&v)[kChunk], int lane)
+{
+    static_assert(kChunk == 8, "reduce-scatter is written for 8 values");
+    unsigned long long a[4], b2[2], c;
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const unsigned long long keep = h5 ? v[4 + i] : v[i], send = h5 ? v[i] : v[4 + i];
+        a[i] = min(keep, shfl_xor64(send, 32));
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const unsigned long long keep = h4 ? a[2 + i] : a[i], send = h4 ? a[i] : a[2 + i];
+        b2[i] = min(keep, shfl_xor64(send, 16));
+    }
+    {
+        const unsigned long long keep = h3 ? b2[1] : b2[0], send = h3 ? b2[0] : b2[1];
+        c = min(keep, shfl_xor64(send, 8));
+    }
+#pragma unroll
+    for (int m = 4; m >= 1; m >>= 1) c = min(c, shfl_xor64(c, m));
+    return c;
+}
+
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_step1_units(const SpaceView *__restrict__ plans, const BatchFrameDev *__restrict__ frames,
+              const UnitDev *__restrict__ units, const int *__restrict__ chunk_frames,
+              int n_units, int rec_max, char *ws, unsigned long long *__restrict__ item_min)
+{
+    constexpr int NW = BS / kWave;
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned long long *rec = reinterpret_cast<unsigned long long *>(lds);
+    uint16_t *srid = reinterpret_cast<uint16_t *>(lds + 8 * kRecRow * rec_max);
+    __shared__ long long ssat[kChunk];                  // SAT byte offsets in ws
+    __shared__ int sbase[kChunk];
+    __shared__ unsigned long long red[kChunk][NW];
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int G = gridDim.x, b = xcd_item(blockIdx.x, G);
+    const int beg = (int)((long long)n_units * b / G), end = (int)((long long)n_units * (b + 1) / G);
+    for (int u = beg; u < end; u++) {
+        const UnitDev ud = units[u];
+        const SpaceView &sp = plans[ud.plan];
+        const ItemDev it = sp.items[ud.item];
+        const int n = it.n_ent, T = it.T;
+        __syncthreads();                                // the previous unit's LDS is read
+        // the item's record indices go to LDS in 16-byte pieces (arrays are 16-byte aligned
+        // and padded); the first piece of each thread is loaded now and stored after the
+        // record build, so its latency overlaps that work
+        const gptr<u32x4> rsrc = as_global(reinterpret_cast<const u32x4 *>(sp.ent_rid + it.rid_off));
+        const int nv = (n * T + 7) >> 3;
+        u32x4 piece = {0u, 0u, 0u, 0u};
+        if (tid < nv) piece = rsrc[tid];
+        if (tid < kChunk) {
+            // an empty slot reads the chunk's first frame; its minimum is not written
+            const int f = chunk_frames[ud.chunk * kChunk + tid];
+            ssat[tid] = frames[f >= 0 ? f : chunk_frames[ud.chunk * kChunk]].o_satT;
+            sbase[tid] = f >= 0 ? frames[f].item_base : -1;
+        }
+        __syncthreads();
+        // phase 1: one record per thread, all frames of the chunk
+        const int S = sp.W + 1;
+        const gptr<uint32_t> rdesc = as_global(sp.rdesc + 2 * it.rec_off);
+        for (int rid = tid; rid < it.n_rec; rid += BS) {
+            const uint32_t d0 = rdesc[2 * rid];
+            const int opt = (int)rdesc[2 * rid + 1];
+            const int xa = d0 & 511, xb = (d0 >> 9) & 511, y0 = (int)(d0 >> 18);
+            const int k = as_global(sp.opt_k)[opt];
+            const gptr<uint16_t> z = as_global(sp.opt_z + (long long)opt * (sp.Km + 1));
+            unsigned long long tmax[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; j++) tmax[j] = 0;
+            for (int q = 0; q < k; q++) {
+                const int ya = y0 + z[q], yb = y0 + z[q + 1];
+                const int i00 = ya * S + xa, i01 = ya * S + xb, i10 = yb * S + xa, i11 = yb * S + xb;
+                long long c[kChunk][4];                 // every corner load issued before use
+#pragma unroll
+                for (int j = 0; j < kChunk; j++) {
+                    const gptr<long long> st = as_global(reinterpret_cast<const long long *>(ws + ssat[j]));
+                    c[j][0] = st[i11];
+                    c[j][1] = st[i01];
+                    c[j][2] = st[i10];
+                    c[j][3] = st[i00];
+                }
+#pragma unroll
+                for (int j = 0; j < kChunk; j++)
+                    tmax[j] = max(tmax[j], (unsigned long long)(c[j][0] - c[j][1] - c[j][2] + c[j][3]));
+            }
+#pragma unroll
+            for (int j = 0; j < kChunk; j++) rec[rid * kRecRow + j] = tmax[j];
+        }
+        {
+            u32x4 *dst = reinterpret_cast<u32x4 *>(srid);
+            if (tid < nv) dst[tid] = piece;
+            for (int v = tid + BS; v < nv; v += BS) dst[v] = rsrc[v];
+        }
+        __syncthreads();
+        // phase 2: one candidate per lane, every frame of the chunk at once
+        unsigned long long tmin[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; j++) tmin[j] = kNone;
+        for (int e = tid; e < n; e += BS) {
+            unsigned long long cur[kChunk];
+#pragma unroll
+            for (int j = 0; j < kChunk; j++) cur[j] = 0;
+#pragma unroll 2
+            for (int t = 0; t < T; t++) {
+                const unsigned long long *row = rec + (int)srid[t * n + e] * kRecRow;
+#pragma unroll
+                for (int j = 0; j < kChunk; j++) cur[j] = max(cur[j], row[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < kChunk; j++) tmin[j] = min(tmin[j], cur[j]);
+        }
+        const unsigned long long v = wave_min8(tmin, lane);
+        if ((lane & 7) == 0) red[(lane >> 3) & 7][wv] = v;
+        __syncthreads();
+        if (tid < kChunk && sbase[tid] >= 0) {
+            unsigned long long m = kNone;
+            for (int w = 0; w < NW; w++) m = min(m, red[tid][w]);
+            item_min[sbase[tid] + ud.item] = m;
+        }
     }
 }
 
@@ -1033,18 +1213,32 @@ k_final_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restri
                      fr.dt, fr.dr);
 }
 
+inline void mark(const hipEvent_t *ev, int i, hipStream_t s)
+{
+    if (ev) (void)hipEventRecord(ev[i], s);
+}
+
 template <int BS>
-void launch_batch_search(const BatchLaunch &b, char *ws, hipStream_t s)
+void launch_batch_search(const BatchLaunch &b, char *ws, hipStream_t s, const hipEvent_t *ev)
 {
     auto *imin = reinterpret_cast<unsigned long long *>(ws + b.o_item_min);
     auto *part = reinterpret_cast<Partial *>(ws + b.o_part);
-    hipLaunchKernelGGL((k_search_batch<BS, false>), dim3(b.grid1), dim3(BS),
-                       batch_lds_bytes(b.rec_max, false), s, b.plans, b.frames, b.item_frame,
-                       b.total_items, ws, imin, part, b.rec_max);
-    hipLaunchKernelGGL(k_tmin_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, imin, ws);
+    auto *live = reinterpret_cast<int *>(ws + b.o_live);
+    auto *live_n = reinterpret_cast<int *>(ws + b.o_live_n);
+    if (b.units)
+        hipLaunchKernelGGL(k_step1_units<BS>, dim3(b.grid_u), dim3(BS), unit_lds_bytes(b.rec_max, b.rid_max),
+                           s, b.plans, b.frames, b.units, b.chunk_frames, b.n_units, b.rec_max, ws, imin);
+    else
+        hipLaunchKernelGGL((k_search_batch<BS, false>), dim3(b.grid1), dim3(BS),
+                           batch_lds_bytes(b.rec_max, false), s, b.plans, b.frames, b.item_frame,
+                           b.total_items, ws, imin, part, b.rec_max, live, live_n);
+    mark(ev, 3, s);
+    hipLaunchKernelGGL(k_tmin_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, imin, ws, part,
+                       live, live_n);
+    mark(ev, 4, s);
     hipLaunchKernelGGL((k_search_batch<BS, true>), dim3(b.grid2), dim3(BS),
                        batch_lds_bytes(b.rec_max, true), s, b.plans, b.frames, b.item_frame,
-                       b.total_items, ws, imin, part, b.rec_max);
+                       b.total_items, ws, imin, part, b.rec_max, live, live_n);
 }
 
 template <int BS>
@@ -1057,7 +1251,32 @@ int occupancy_of(int rec_max, bool step2)
         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search_batch<BS, false>, BS, lds);
     return e == hipSuccess && n > 0 ? n : 1;
 }
+
+template <int BS>
+int unit_occupancy_of(int lds)
+{
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step1_units<BS>, BS, lds);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
 }  // namespace
+
+int unit_lds_bytes(int rec_max, int rid_max)
+{
+    const long long bytes = 8ll * kRecRow * (rec_max > 0 ? rec_max : 1) + 2ll * ((rid_max + 7) & ~7);
+    return bytes <= 65536 ? (int)bytes : 0;
+}
+
+int unit_occupancy(int block, int rec_max, int rid_max)
+{
+    const int lds = unit_lds_bytes(rec_max, rid_max);
+    switch (block) {
+    case 64: return unit_occupancy_of<64>(lds);
+    case 128: return unit_occupancy_of<128>(lds);
+    case 512: return unit_occupancy_of<512>(lds);
+    default: return unit_occupancy_of<256>(lds);
+    }
+}
 
 WsLayout ws_layout(const Plan &pl)
 {
@@ -1169,8 +1388,10 @@ int batch_occupancy(int block, int rec_max, bool step2)
     }
 }
 
-hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s)
+hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s,
+                        const hipEvent_t *ev)
 {
+    mark(ev, 0, s);
     switch (b.cs) {
     case 128:
         hipLaunchKernelGGL(k_features_batch<128>, dim3(b.total_ctus), dim3(256), 0, s, b.frames,
@@ -1185,20 +1406,29 @@ hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStre
                            b.ctu_frame, ws);
         break;
     }
-    hipLaunchKernelGGL(k_cost_sat_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, ws);
+    mark(ev, 1, s);
+    hipLaunchKernelGGL(k_cost_sat_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, ws,
+                       reinterpret_cast<int *>(ws + b.o_live_n));
+    mark(ev, 2, s);
     if (b.total_items > 0) {
         switch (b.block) {
-        case 64: launch_batch_search<64>(b, ws, s); break;
-        case 128: launch_batch_search<128>(b, ws, s); break;
-        case 512: launch_batch_search<512>(b, ws, s); break;
-        default: launch_batch_search<256>(b, ws, s); break;
+        case 64: launch_batch_search<64>(b, ws, s, ev); break;
+        case 128: launch_batch_search<128>(b, ws, s, ev); break;
+        case 512: launch_batch_search<512>(b, ws, s, ev); break;
+        default: launch_batch_search<256>(b, ws, s, ev); break;
         }
     } else {
+        mark(ev, 3, s);
         hipLaunchKernelGGL(k_tmin_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames,
-                           reinterpret_cast<unsigned long long *>(ws + b.o_item_min), ws);
+                           reinterpret_cast<unsigned long long *>(ws + b.o_item_min), ws,
+                           reinterpret_cast<Partial *>(ws + b.o_part),
+                           reinterpret_cast<int *>(ws + b.o_live), reinterpret_cast<int *>(ws + b.o_live_n));
+        mark(ev, 4, s);
     }
+    mark(ev, 5, s);
     hipLaunchKernelGGL(k_final_batch, dim3(b.n_frames), dim3(256), 0, s, b.plans, b.frames,
                        reinterpret_cast<const Partial *>(ws + b.o_part), ws, out);
+    mark(ev, 6, s);
     return hipGetLastError();
 }
 

@@ -58,21 +58,39 @@ struct BatchFrameDev {
     long long o_s1, o_grad, o_tex, o_mean, o_var, o_s2, o_cost, o_hdr, o_satT, o_satS1, o_satS2;
 };
 
+// Frame-inner step-1 work unit: one item of one plan for a chunk of up to kChunk frames
+// that share the plan (frame indices in chunk_frames[chunk * kChunk ..], -1 = none).
+constexpr int kChunk = 8;
+struct UnitDev {
+    int plan, item, chunk, pad;
+};
+
 struct BatchLaunch {
     const SpaceView *plans;           // device
     const BatchFrameDev *frames;      // device
     const int *ctu_frame, *item_frame;
+    const UnitDev *units;             // device; null: step 1 runs per (frame, item)
+    const int *chunk_frames;          // device
     int n_frames, total_ctus, total_items, cs;
     int block, grid1, grid2, rec_max;
+    int n_units, grid_u, rid_max, pad;
     long long o_item_min, o_part;     // byte offsets in the workspace
+    long long o_live, o_live_n;       // step-2 list of live (frame, item) entries and its length
 };
+
+// Dynamic LDS of the frame-inner step-1 kernel, or 0 when the records and record indices
+// of the largest item do not fit.
+int unit_lds_bytes(int rec_max, int rid_max);
+int unit_occupancy(int block, int rec_max, int rid_max);
 
 // Byte layout of one frame's region and its size (W x H CTUs).
 long long batch_frame_region(int W, int H, BatchFrameDev *fr, long long base);
 int batch_lds_bytes(int rec_max, bool step2);
 // Work-groups per CU the batched search kernels can keep resident.
 int batch_occupancy(int block, int rec_max, bool step2);
-hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s);
+// ev (nullable): 7 events recorded before the first launch and after each of the six
+hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s,
+                        const hipEvent_t *ev = nullptr);
 
 hipError_t launch_features(int w, int h, int cs, const uint16_t *luma, int64_t stride,
                            const trs_feat &out, hipStream_t s);

@@ -439,6 +439,9 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
                 pl.ent_rid.resize(base + (size_t)n * T);
                 for (int e = 0; e < n; e++)
                     for (int t = 0; t < T; t++) pl.ent_rid[base + (size_t)t * n + e] = cur_rid[(size_t)e * T + t];
+                // every item's array starts on 16 bytes and may be read in 16-byte pieces
+                pl.ent_rid.resize((pl.ent_rid.size() + 7) & ~size_t(7), 0);
+                pl.rid_max = std::max(pl.rid_max, (int32_t)(((int64_t)n * T + 7) & ~int64_t(7)));
                 pl.rdesc.insert(pl.rdesc.end(), cur_desc.begin(), cur_desc.end());
                 pl.items.push_back(it);
                 pl.rec_max = std::max(pl.rec_max, it.n_rec);

@@ -71,7 +71,8 @@ struct SpaceView {
     const int32_t *unif_rs;            // [n_unif * 4]
     int32_t W, H, N, Km, n_items, n_shapes, n_unif, pad;
     int32_t cu, ru;                    // uniform grid shape
-    int32_t rec_max, pad2;             // largest per-item record count
+    int32_t rec_max;                   // largest per-item record count
+    int32_t rid_max;                   // largest per-item n_ent * T, rounded up to 8
     int64_t total, uniform_rank, n_feasible;
 };
 
@@ -98,6 +99,7 @@ struct Plan {
     std::vector<int32_t> unif_rs;
     int64_t uniform_rank = -1;
     int32_t rec_max = 0;               // largest record count of an item (LDS records)
+    int32_t rid_max = 0;               // largest n_ent * T of an item, rounded up to 8
     int64_t n_feasible = 0;            // area-feasible candidates
     int64_t tile_lookups = 0, records = 0, record_slices = 0;
     // device copy

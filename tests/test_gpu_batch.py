@@ -131,3 +131,28 @@ def test_batch_with_infeasible_frame(orc):
         ref = orc.partition(fr["luma_np"], fr["prev_np"], oracle_params(orc, fr["params"]))
         assert_same_result(got[i], ref, f"frame {i}")
     batch.close()
+
+
+def test_batch_profile_events(orc):
+    """Event timing around the six batch launches: one record per run, every stage timed,
+    results unchanged by profiling."""
+    import torch
+    frames = _mixed_frames(orc, SPEC[:3])
+    batch = B.Batch(frames)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    ref = batch.out.clone()
+    B.trs_profile_read_batch()                       # drop anything recorded earlier
+    B.trs_profile_enable(True)
+    try:
+        batch.enqueue()
+        batch.enqueue()
+    finally:
+        B.trs_profile_enable(False)
+    ms, runs = B.trs_profile_read_batch()
+    assert runs == 2
+    assert set(ms) == set(B.BATCH_STAGES)
+    assert all(v > 0 for v in ms.values())
+    assert torch.equal(batch.out, ref)
+    assert B.trs_profile_read_batch() == ({k: 0.0 for k in B.BATCH_STAGES}, 0)
+    batch.close()
