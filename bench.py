@@ -59,6 +59,8 @@ def main():
                     help="uhd_seq: the 64-frame 4K sequence; batch512: 512 mixed frames in one batch; "
                          "mlp: training steps of the learned CTU-time predictor")
     ap.add_argument("--mlp-batch", type=int, default=65536)
+    ap.add_argument("--split", type=int, default=0,
+                    help="batched form: sub-batches on their own streams (0: tuned, else 1)")
     ap.add_argument("--form", default="batched", choices=["batched", "streams"],
                     help="4K sequence: one batched launch sequence per step, or per-frame launches "
                          "over --streams streams")
@@ -156,17 +158,38 @@ def main():
     tuned = (autotune.load(f"{autotune.arch()}|uhd_seq{F}") or {}) if not args.sched_block else {}
     block = args.sched_block or tuned.get("block", 0)
     wgs = args.wgs_per_cu or tuned.get("wgs_per_cu", 0)
-    batch = B.Batch([dict(width=w, height=h, params=params, luma=luma[f], prev=prev[f]) for f in range(F)],
-                    block=block, wgs_per_cu=wgs)
+    # K sub-batches of consecutive frames, one stream each: one sub-batch's HBM-bound feature
+    # kernel can run beside another's latency-bound search kernels
+    K = max(1, min(F, args.split or tuned.get("split", 1)))
+    cuts = [F * k // K for k in range(K + 1)]
+    batches = [B.Batch([dict(width=w, height=h, params=params, luma=luma[f], prev=prev[f])
+                        for f in range(cuts[k], cuts[k + 1])], block=block, wgs_per_cu=wgs) for k in range(K)]
+    bstreams = [torch.cuda.Stream() for _ in range(K)] if K > 1 else None
+
+    def step_batch():
+        if K == 1:
+            batches[0].enqueue()
+            return
+        base = torch.cuda.current_stream()
+        for st in bstreams:
+            st.wait_stream(base)
+        for bt, st in zip(batches, bstreams):
+            bt.enqueue(stream=st)
+        for st in bstreams:
+            base.wait_stream(st)
+
+    def batch_out():
+        return torch.cat([bt.out for bt in batches])
+
     for _ in range(max(args.warmup, 1)):
-        batch.enqueue()
+        step_batch()
     torch.cuda.synchronize()
-    g_batch = batch.capture()
+    g_batch = capture(step_batch)
 
     fps_streams, el_streams = time_graph(g_streams, args.warmup, args.steps, F)
     outs_streams = outs.clone()
     fps_batch, el_batch = time_graph(g_batch, args.warmup, args.steps, F)
-    outs_batch = batch.out.clone()
+    outs_batch = batch_out()
     log(f"per-frame launches over {S} streams: {fps_streams:.1f} frames/s; batched: {fps_batch:.1f} frames/s")
     batched = args.form == "batched"
     fps, elapsed = (fps_batch, el_batch) if batched else (fps_streams, el_streams)
@@ -179,14 +202,14 @@ def main():
     t0 = time.perf_counter()
     if batched:
         for _ in range(args.steps):
-            batch.enqueue()
+            step_batch()
         torch.cuda.synchronize()
         eager_elapsed = time.perf_counter() - t0
         B.trs_profile_enable(False)
         stage_ms, runs = B.trs_profile_read_batch()
         kms = {k: v / max(runs, 1) for k, v in stage_ms.items()}
-        eager_out = batch.out
-        launch_frames = F
+        eager_out = batch_out()
+        launch_frames = F / K
     else:
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(F)]
         feat_ms = 0.0
@@ -297,8 +320,9 @@ def main():
                                f"{stats['candidates']} candidates/frame ({stats['feasible']} area-feasible)",
                    "frames": F, "width": w, "height": h, "n_threads": 8,
                    "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
-                   "form": args.form,
-                   "timing": (f"HIP graph of one step (one trs_batch_run over the {F} frames), replayed K times"
+                   "form": args.form, "sub_batches": K if batched else None,
+                   "timing": (f"HIP graph of one step ({K} trs_batch_run over {F} frames, one stream each), "
+                              f"replayed once per step"
                               if batched else
                               f"HIP graph of one step ({F} trs_partition calls over {S} streams), replayed K times")},
         "candidates_scored_per_s": round(fps * stats["candidates"], 1),

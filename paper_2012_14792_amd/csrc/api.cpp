@@ -112,6 +112,7 @@ trs_status device_view(PlanEntry &e, trs::SpaceView *view)
     size_t o_entf = add_array(parts, off, pl.ent_f);
     size_t o_entr = add_array(parts, off, pl.ent_rid);
     size_t o_rdesc = add_array(parts, off, pl.rdesc);
+    size_t o_rdesc4 = add_array(parts, off, pl.rdesc4);
     size_t o_unif = add_array(parts, off, pl.unif_rs);
     const size_t bytes = (off + 255) & ~size_t(255);
     std::vector<char> host(bytes, 0);
@@ -142,6 +143,8 @@ trs_status device_view(PlanEntry &e, trs::SpaceView *view)
     v.ent_f = reinterpret_cast<const uint32_t *>(b + o_entf);
     v.ent_rid = reinterpret_cast<const uint16_t *>(b + o_entr);
     v.rdesc = reinterpret_cast<const uint32_t *>(b + o_rdesc);
+    v.rdesc4 = reinterpret_cast<const uint32_t *>(b + o_rdesc4);
+    v.compact = pl.compact;
     v.unif_rs = reinterpret_cast<const int32_t *>(b + o_unif);
     v.W = pl.W;
     v.H = pl.H;
@@ -395,7 +398,8 @@ trs_status trs_search_stats(const trs_frame *frame, const trs_search_params *par
     out->record_slices = pl.record_slices;
     out->table_bytes = (int64_t)(pl.combos.size() * 2 + pl.xtab.size() * 2 + pl.ytab.size() * 2 +
                                  pl.items.size() * sizeof(trs::ItemDev) + pl.ent_f.size() * 4 +
-                                 pl.ent_rid.size() * 2 + pl.rdesc.size() * 4 + pl.opt_z.size() * 2);
+                                 pl.ent_rid.size() * 2 + pl.rdesc.size() * 4 + pl.rdesc4.size() * 4 +
+                                 pl.opt_z.size() * 2);
     out->feasible = pl.n_feasible;
     out->dtile = pl.dt;
     out->drs = pl.dr;
@@ -497,23 +501,31 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     // frame-inner step-1 units: frames grouped by plan into chunks of kChunk, units ordered
     // item-major so one work-group's range revisits an item's tables chunk after chunk
     std::vector<trs::UnitDev> units;
-    std::vector<int> chunk_frames;
-    const bool use_units = trs::unit_lds_bytes(rec_max, rid_max) > 0;
+    std::vector<trs::ChunkSlot> slots;
+    bool use_units = trs::unit_lds_bytes(rec_max, rid_max) > 0;
+    for (const trs::SpaceView &v : views) use_units = use_units && v.compact;
     if (use_units) {
         for (int p = 0; p < (int)views.size(); p++) {
             std::vector<int> fl;
             for (int f = 0; f < n_frames; f++)
                 if (b->frames[f].plan == p) fl.push_back(f);
-            const int c0 = (int)(chunk_frames.size() / trs::kChunk);
+            const int c0 = (int)(slots.size() / trs::kChunk);
             const int nc = ((int)fl.size() + trs::kChunk - 1) / trs::kChunk;
             for (int c = 0; c < nc; c++)
                 for (int j = 0; j < trs::kChunk; j++) {
                     const int q = c * trs::kChunk + j;
-                    chunk_frames.push_back(q < (int)fl.size() ? fl[q] : -1);
+                    const bool in = q < (int)fl.size();
+                    const trs::BatchFrameDev &fd = b->frames[in ? fl[q] : fl[c * trs::kChunk]];
+                    slots.push_back(trs::ChunkSlot{fd.o_satT, in ? fd.item_base : -1, 0});
                 }
-            const int n_items = (int)plan_of_view[p]->plan->items.size();
-            for (int i = 0; i < n_items; i++)
-                for (int c = 0; c < nc; c++) units.push_back(trs::UnitDev{p, i, c0 + c, 0});
+            const trs::Plan &pl = *plan_of_view[p]->plan;
+            const trs::SpaceView &v = views[p];
+            for (int i = 0; i < (int)pl.items.size(); i++) {
+                const trs::ItemDev &it = pl.items[i];
+                for (int c = 0; c < nc; c++)
+                    units.push_back(trs::UnitDev{v.ent_rid + it.rid_off, v.rdesc4 + 4 * it.rec_off, it.n_ent,
+                                                 it.n_rec, it.T, pl.W + 1, i, c0 + c, 0, 0});
+            }
         }
         if (units.size() > (size_t)INT32_MAX / 2) return TRS_ENOSPACE;
     }
@@ -525,7 +537,7 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     size_t o_cf = add_array(parts, boff, ctu_frame);
     size_t o_if = add_array(parts, boff, item_frame);
     size_t o_units = add_array(parts, boff, units);
-    size_t o_chf = add_array(parts, boff, chunk_frames);
+    size_t o_slots = add_array(parts, boff, slots);
     const size_t bytes = (boff + 255) & ~size_t(255);
     std::vector<char> host(bytes, 0);
     for (auto &pt : parts)
@@ -542,7 +554,7 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     L.ctu_frame = reinterpret_cast<const int *>(bp + o_cf);
     L.item_frame = reinterpret_cast<const int *>(bp + o_if);
     L.units = use_units ? reinterpret_cast<const trs::UnitDev *>(bp + o_units) : nullptr;
-    L.chunk_frames = use_units ? reinterpret_cast<const int *>(bp + o_chf) : nullptr;
+    L.slots = use_units ? reinterpret_cast<const trs::ChunkSlot *>(bp + o_slots) : nullptr;
     L.n_units = (int)units.size();
     L.n_frames = n_frames;
     L.total_ctus = (int)ctu_frame.size();

@@ -52,6 +52,11 @@ __device__ __forceinline__ long long wave_incl_scan(long long v, int lane)
     return v;
 }
 
+// Pointers read from device tables are generic; these views tell the compiler they address
+// global memory, so loads through them are global (not flat) loads.
+template <class T> using gptr = const __attribute__((address_space(1))) T *;
+template <class T> __device__ __forceinline__ gptr<T> as_global(const T *p) { return (gptr<T>)p; }
+
 __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -95,16 +100,23 @@ __device__ __forceinline__ void features_ctu(const uint16_t *__restrict__ luma, 
         const bool has_right = x0 + 8 < w;
         const int nrow = min(R + 1, h - ybase);         // rows present, incl. the halo row
         // issue every load of this thread before using any of them
-        uint4 v[R + 1];
+        u32x4 v[R + 1];
         uint32_t right[R];
-        const uint16_t *row0 = luma + (long long)ybase * stride + x0;
+        const gptr<uint16_t> row0 = as_global(luma + (long long)ybase * stride + x0);
 #pragma unroll
         for (int r = 0; r <= R; r++)
-            v[r] = r < nrow ? *reinterpret_cast<const uint4 *>(row0 + (long long)r * stride)
-                            : make_uint4(0, 0, 0, 0);
+            v[r] = r < nrow ? *reinterpret_cast<const gptr<u32x4>>(row0 + (long long)r * stride)
+                            : u32x4{0u, 0u, 0u, 0u};
+        // the sample right of the chunk is the first sample of the next lane's chunk (lanes of
+        // one CTU row form one 16-lane DPP row), except for the row's last chunk
+        const bool last = chunk == CH - 1;
 #pragma unroll
-        for (int r = 0; r < R; r++)
-            right[r] = (r < nrow && has_right) ? (uint32_t)row0[(long long)r * stride + 8] : 0u;
+        for (int r = 0; r < R; r++) {
+            uint32_t nb = 0;
+            if (CH == 16) nb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[r].x, 0x101, 0xf, 0xf, false) & 0xffffu;
+            const bool load = CH != 16 || last;
+            right[r] = (r < nrow && has_right) ? (load ? (uint32_t)row0[(long long)r * stride + 8] : nb) : 0u;
+        }
         if (nv == 8) {
             // Full chunk: samples stay packed two per 32-bit word.  sad_u16 adds the
             // absolute differences of both 16-bit halves, udot2 the products of both halves.
@@ -1064,10 +1076,6 @@ k_tmin_batch(const BatchFrameDev *__restrict__ frames,
 // updates all frames' running maxima from that row.  Writes item_min for each frame.
 constexpr int kRecRow = kChunk + 2;                     // u64 per record row (16-byte rows)
 
-// Pointers read from device tables are generic; these views tell the compiler they address
-// global memory, so loads through them are global (not flat) loads.
-template <class T> using gptr = const __attribute__((address_space(1))) T *;
-template <class T> __device__ __forceinline__ gptr<T> as_global(const T *p) { return (gptr<T>)p; }
 
 // Minimum over the work-group's wave of each of kChunk values per lane, reduce-scattered:
 // after the three halving exchanges lane l holds the partial of value (l >> 3) & 7 over 8
@@ -1099,59 +1107,51 @@ __device__ __forceinline__ unsigned long long wave_min8(const unsigned long long
 
 template <int BS>
 __global__ void __launch_bounds__(BS)
-k_step1_units(const SpaceView *__restrict__ plans, const BatchFrameDev *__restrict__ frames,
-              const UnitDev *__restrict__ units, const int *__restrict__ chunk_frames,
-              int n_units, int rec_max, char *ws, unsigned long long *__restrict__ item_min)
+k_step1_units(const UnitDev *__restrict__ units, const ChunkSlot *__restrict__ slots, int n_units,
+              int rec_max, char *ws, unsigned long long *__restrict__ item_min)
 {
     constexpr int NW = BS / kWave;
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned long long *rec = reinterpret_cast<unsigned long long *>(lds);
     uint16_t *srid = reinterpret_cast<uint16_t *>(lds + 8 * kRecRow * rec_max);
-    __shared__ long long ssat[kChunk];                  // SAT byte offsets in ws
-    __shared__ int sbase[kChunk];
     __shared__ unsigned long long red[kChunk][NW];
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int G = gridDim.x, b = xcd_item(blockIdx.x, G);
     const int beg = (int)((long long)n_units * b / G), end = (int)((long long)n_units * (b + 1) / G);
+    if (beg >= end) return;
+    UnitDev next = units[beg];
     for (int u = beg; u < end; u++) {
-        const UnitDev ud = units[u];
-        const SpaceView &sp = plans[ud.plan];
-        const ItemDev it = sp.items[ud.item];
-        const int n = it.n_ent, T = it.T;
+        const UnitDev ud = next;
+        if (u + 1 < end) next = units[u + 1];           // used by the next iteration
+        const int n = ud.n_ent, T = ud.T, S = ud.S;
+        const ChunkSlot *sl = slots + ud.chunk * kChunk;
         __syncthreads();                                // the previous unit's LDS is read
         // the item's record indices go to LDS in 16-byte pieces (arrays are 16-byte aligned
-        // and padded); the first piece of each thread is loaded now and stored after the
-        // record build, so its latency overlaps that work
-        const gptr<u32x4> rsrc = as_global(reinterpret_cast<const u32x4 *>(sp.ent_rid + it.rid_off));
+        // and padded); each thread's first piece is stored after the record build
+        const gptr<u32x4> rsrc = as_global(reinterpret_cast<const u32x4 *>(ud.rids));
         const int nv = (n * T + 7) >> 3;
         u32x4 piece = {0u, 0u, 0u, 0u};
         if (tid < nv) piece = rsrc[tid];
-        if (tid < kChunk) {
-            // an empty slot reads the chunk's first frame; its minimum is not written
-            const int f = chunk_frames[ud.chunk * kChunk + tid];
-            ssat[tid] = frames[f >= 0 ? f : chunk_frames[ud.chunk * kChunk]].o_satT;
-            sbase[tid] = f >= 0 ? frames[f].item_base : -1;
-        }
-        __syncthreads();
-        // phase 1: one record per thread, all frames of the chunk
-        const int S = sp.W + 1;
-        const gptr<uint32_t> rdesc = as_global(sp.rdesc + 2 * it.rec_off);
-        for (int rid = tid; rid < it.n_rec; rid += BS) {
-            const uint32_t d0 = rdesc[2 * rid];
-            const int opt = (int)rdesc[2 * rid + 1];
-            const int xa = d0 & 511, xb = (d0 >> 9) & 511, y0 = (int)(d0 >> 18);
-            const int k = as_global(sp.opt_k)[opt];
-            const gptr<uint16_t> z = as_global(sp.opt_z + (long long)opt * (sp.Km + 1));
+        // phase 1: one record per thread, all frames of the chunk; a record's corner loads
+        // for every frame are issued before any is used
+        const gptr<u32x4> rd = as_global(reinterpret_cast<const u32x4 *>(ud.rdesc4));
+        for (int rid = tid; rid < ud.n_rec; rid += BS) {
+            const u32x4 d = rd[rid];
+            const int xa = d.x & 511, xb = (d.x >> 9) & 511, y0 = (int)(d.x >> 18);
+            const int k = d.y & 255;
             unsigned long long tmax[kChunk];
 #pragma unroll
             for (int j = 0; j < kChunk; j++) tmax[j] = 0;
+            int ya = y0;
             for (int q = 0; q < k; q++) {
-                const int ya = y0 + z[q], yb = y0 + z[q + 1];
+                const int zi = q + 1;                   // byte zi of words 1..3
+                const uint32_t wsel = zi < 4 ? d.y : zi < 8 ? d.z : d.w;
+                const int yb = y0 + (int)((wsel >> (8 * (zi & 3))) & 255);
                 const int i00 = ya * S + xa, i01 = ya * S + xb, i10 = yb * S + xa, i11 = yb * S + xb;
-                long long c[kChunk][4];                 // every corner load issued before use
+                long long c[kChunk][4];
 #pragma unroll
                 for (int j = 0; j < kChunk; j++) {
-                    const gptr<long long> st = as_global(reinterpret_cast<const long long *>(ws + ssat[j]));
+                    const gptr<long long> st = as_global(reinterpret_cast<const long long *>(ws + sl[j].o_sat));
                     c[j][0] = st[i11];
                     c[j][1] = st[i01];
                     c[j][2] = st[i10];
@@ -1160,6 +1160,7 @@ k_step1_units(const SpaceView *__restrict__ plans, const BatchFrameDev *__restri
 #pragma unroll
                 for (int j = 0; j < kChunk; j++)
                     tmax[j] = max(tmax[j], (unsigned long long)(c[j][0] - c[j][1] - c[j][2] + c[j][3]));
+                ya = yb;
             }
 #pragma unroll
             for (int j = 0; j < kChunk; j++) rec[rid * kRecRow + j] = tmax[j];
@@ -1190,10 +1191,13 @@ k_step1_units(const SpaceView *__restrict__ plans, const BatchFrameDev *__restri
         const unsigned long long v = wave_min8(tmin, lane);
         if ((lane & 7) == 0) red[(lane >> 3) & 7][wv] = v;
         __syncthreads();
-        if (tid < kChunk && sbase[tid] >= 0) {
-            unsigned long long m = kNone;
-            for (int w = 0; w < NW; w++) m = min(m, red[tid][w]);
-            item_min[sbase[tid] + ud.item] = m;
+        if (tid < kChunk) {
+            const int base = sl[tid].item_base;
+            if (base >= 0) {
+                unsigned long long m = kNone;
+                for (int w = 0; w < NW; w++) m = min(m, red[tid][w]);
+                item_min[base + ud.item] = m;
+            }
         }
     }
 }
@@ -1227,7 +1231,7 @@ void launch_batch_search(const BatchLaunch &b, char *ws, hipStream_t s, const hi
     auto *live_n = reinterpret_cast<int *>(ws + b.o_live_n);
     if (b.units)
         hipLaunchKernelGGL(k_step1_units<BS>, dim3(b.grid_u), dim3(BS), unit_lds_bytes(b.rec_max, b.rid_max),
-                           s, b.plans, b.frames, b.units, b.chunk_frames, b.n_units, b.rec_max, ws, imin);
+                           s, b.units, b.slots, b.n_units, b.rec_max, ws, imin);
     else
         hipLaunchKernelGGL((k_search_batch<BS, false>), dim3(b.grid1), dim3(BS),
                            batch_lds_bytes(b.rec_max, false), s, b.plans, b.frames, b.item_frame,

@@ -59,10 +59,19 @@ struct BatchFrameDev {
 };
 
 // Frame-inner step-1 work unit: one item of one plan for a chunk of up to kChunk frames
-// that share the plan (frame indices in chunk_frames[chunk * kChunk ..], -1 = none).
+// that share the plan.  It carries what the kernel needs of the item, so one load starts it.
 constexpr int kChunk = 8;
 struct UnitDev {
-    int plan, item, chunk, pad;
+    const uint16_t *rids;             // the item's record indices [T][n_ent], 16-byte aligned
+    const uint32_t *rdesc4;           // the item's compact record descriptors
+    int n_ent, n_rec, T, S;           // S = W + 1, the SAT row length
+    int item, chunk, pad0, pad1;
+};
+// One frame slot of a chunk: its SAT of predicted times (byte offset in the workspace) and
+// its first item in the flat item list (-1: empty slot, which reads the chunk's first frame).
+struct ChunkSlot {
+    long long o_sat;
+    int item_base, pad;
 };
 
 struct BatchLaunch {
@@ -70,7 +79,7 @@ struct BatchLaunch {
     const BatchFrameDev *frames;      // device
     const int *ctu_frame, *item_frame;
     const UnitDev *units;             // device; null: step 1 runs per (frame, item)
-    const int *chunk_frames;          // device
+    const ChunkSlot *slots;           // device, kChunk per chunk
     int n_frames, total_ctus, total_items, cs;
     int block, grid1, grid2, rec_max;
     int n_units, grid_u, rid_max, pad;

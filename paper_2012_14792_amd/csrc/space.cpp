@@ -525,6 +525,29 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
     }
     if (rank_base != pl.total) return TRS_EINVAL;            // two counts must agree
 
+    // Compact record descriptors: the option's split rows inline, so a record is one load.
+    {
+        const size_t nrec = pl.rdesc.size() / 2;
+        bool ok = true;
+        std::vector<uint32_t> d4(nrec * 4, 0);
+        for (size_t q = 0; q < nrec && ok; q++) {
+            const int opt = (int)pl.rdesc[2 * q + 1];
+            const int k = pl.opt_k[opt];
+            const uint16_t *z = &pl.opt_z[(size_t)opt * (Km + 1)];
+            if (k > 11 || z[k] > 255) { ok = false; break; }
+            uint8_t bytes[12] = {0};
+            bytes[0] = (uint8_t)k;
+            for (int i = 1; i <= k; i++) bytes[i] = (uint8_t)z[i];
+            d4[4 * q] = pl.rdesc[2 * q];
+            for (int w = 0; w < 3; w++)
+                d4[4 * q + 1 + w] = (uint32_t)bytes[4 * w] | ((uint32_t)bytes[4 * w + 1] << 8) |
+                                    ((uint32_t)bytes[4 * w + 2] << 16) | ((uint32_t)bytes[4 * w + 3] << 24);
+        }
+        pl.compact = ok ? 1 : 0;
+        if (ok) pl.rdesc4.swap(d4);
+        else pl.rdesc4.clear();
+    }
+
     // The uniform grid (Section 3.2): c_u r_u = N, most square, c_u >= r_u, one RS per tile.
     pl.ru = 1;
     for (int d = 1; d * d <= N; d++) if (N % d == 0) pl.ru = d;

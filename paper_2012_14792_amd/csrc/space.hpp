@@ -68,11 +68,13 @@ struct SpaceView {
     const uint32_t *ent_f;             // per entry: (x - xa) * M + m
     const uint16_t *ent_rid;           // per item [T][n_ent] record indices
     const uint32_t *rdesc;             // per record: two words (see ItemDev)
+    const uint32_t *rdesc4;            // per record: four words, the split rows inline (see Plan)
     const int32_t *unif_rs;            // [n_unif * 4]
     int32_t W, H, N, Km, n_items, n_shapes, n_unif, pad;
     int32_t cu, ru;                    // uniform grid shape
     int32_t rec_max;                   // largest per-item record count
     int32_t rid_max;                   // largest per-item n_ent * T, rounded up to 8
+    int32_t compact, pad3;             // 1: rdesc4 holds every record
     int64_t total, uniform_rank, n_feasible;
 };
 
@@ -95,6 +97,11 @@ struct Plan {
     std::vector<uint32_t> ent_f;
     std::vector<uint16_t> ent_rid;
     std::vector<uint32_t> rdesc;
+    // Per record, four words: word 0 as in rdesc; words 1..3 the slice count k (low byte)
+    // and the split rows z_1 .. z_k of the option (one byte each, z_k = tile height).
+    // Filled only when every record has k <= 11 and tile heights <= 255 (compact = 1).
+    std::vector<uint32_t> rdesc4;
+    int32_t compact = 0;
     int32_t cu = 0, ru = 0, n_unif = 0;
     std::vector<int32_t> unif_rs;
     int64_t uniform_rank = -1;
