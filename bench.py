@@ -33,9 +33,13 @@ sys.path.insert(0, ROOT)
 
 PEAK_ALU_TOPS = round(256 * 64 * 2.4e9 / 1e12, 2)   # 32-bit VALU lane-ops: CUs x lanes/clk x clock
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE on this workload, scaled by the
-# copy-kernel calibration; None where the kernel changed since the counters were taken.
-TRAFFIC = {}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.00) + WRITE_SIZE (x 1.00) on this workload,
+# the factors read from a 1 GiB device copy in the same runs; a kernel changed since the
+# counters were taken has no entry.
+TRAFFIC = {
+    "k_features_batch<128>": 1223334195,     # 64 frames: 596,811.9 KiB fetched, 1,038.5 KiB written
+    "k_features<128>": 16889037,             # 1 frame: 8,239.5 KiB fetched, 14.2 KiB written
+}
 METRIC = "4K frames partitioned/s + TRS candidates scored/s (1 GPU, bit-exact vs oracle)"
 
 

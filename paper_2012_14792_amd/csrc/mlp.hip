@@ -7,7 +7,7 @@
 //   k_mlp_bwd_data    per-sample dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1)
 //   k_mlp_bwd_w       weight gradients: each work-group sums its sample chunk into one
 //                     partial (entries spread over threads, samples staged in LDS tiles)
-//   k_mlp_reduce      partials summed in work-group order (deterministic)
+//   k_mlp_reduce      partials summed in a fixed order, one wave per entry (deterministic)
 //   k_mlp_cost        prediction -> u32 microseconds, or the plain blend per CTU when the
 //                     prediction is not finite or an input is outside the training range
 #include <hip/hip_runtime.h>
@@ -221,13 +221,18 @@ struct Grads {
     float *w1, *b1, *w2, *b2, *w3, *b3;
 };
 
+// One wave per gradient entry: lane l sums partials l, l + 64, .. in order, then a fixed
+// butterfly adds the lanes, so the result repeats exactly.
 __global__ void __launch_bounds__(256)
 k_mlp_reduce(const float *__restrict__ partial, int n_part, Grads g)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= kEntries) return;
+    const int e = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e >= kEntries) return;                         // the whole wave leaves together
     float a = 0.0f;
-    for (int p = 0; p < n_part; p++) a += partial[(long long)p * kEntries + e];
+    for (int p = lane; p < n_part; p += 64) a += partial[(long long)p * kEntries + e];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m, 64);
+    if (lane != 0) return;
     int o = e;
     if (o < kHid * kIn) { g.w1[o] = a; return; }
     o -= kHid * kIn;
@@ -322,7 +327,7 @@ hipError_t launch_mlp_backward(const trs_mlp &m, const trs_mlp_norm &nm, const f
     hipLaunchKernelGGL(k_mlp_bwd_w, dim3(parts), dim3(256), 0, s, nm, x, z1, z2, dz1, dz2, dy, n,
                        (int)chunk, part);
     const Grads gg{g.w1, g.b1, g.w2, g.b2, g.w3, g.b3};
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kEntries + 255) / 256), dim3(256), 0, s, part, parts, gg);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kEntries + 3) / 4), dim3(256), 0, s, part, parts, gg);
     return hipGetLastError();
 }
 
