@@ -496,12 +496,13 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     b->launch.o_item_min = up(off);
     b->launch.o_part = b->launch.o_item_min + up(8 * total_items);
     b->launch.o_live = b->launch.o_part + up((long long)sizeof(trs::Partial) * total_items);
-    b->launch.o_live_n = b->launch.o_live + up(4 * total_items);
+    b->launch.o_live_n = b->launch.o_live + up(8 * total_items);
     b->ws_bytes = (size_t)(b->launch.o_live_n + 256);
     // frame-inner step-1 units: frames grouped by plan into chunks of kChunk, units ordered
     // item-major so one work-group's range revisits an item's tables chunk after chunk
     std::vector<trs::UnitDev> units;
     std::vector<trs::ChunkSlot> slots;
+    std::vector<trs::ItemBrief> briefs;
     bool use_units = trs::unit_lds_bytes(rec_max, rid_max) > 0;
     for (const trs::SpaceView &v : views) use_units = use_units && v.compact;
     if (use_units) {
@@ -520,11 +521,16 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
                 }
             const trs::Plan &pl = *plan_of_view[p]->plan;
             const trs::SpaceView &v = views[p];
+            const int bb = (int)briefs.size();
+            for (int f : fl) b->frames[f].brief_base = bb;
             for (int i = 0; i < (int)pl.items.size(); i++) {
                 const trs::ItemDev &it = pl.items[i];
                 for (int c = 0; c < nc; c++)
                     units.push_back(trs::UnitDev{v.ent_rid + it.rid_off, v.rdesc4 + 4 * it.rec_off, it.n_ent,
                                                  it.n_rec, it.T, pl.W + 1, i, c0 + c, 0, 0});
+                briefs.push_back(trs::ItemBrief{v.ent_rid + it.rid_off, v.rdesc4 + 4 * it.rec_off,
+                                                v.ent_f + it.ent_off, it.rank0, it.SM, it.n_ent, it.n_rec,
+                                                it.T, it.M});
             }
         }
         if (units.size() > (size_t)INT32_MAX / 2) return TRS_ENOSPACE;
@@ -537,6 +543,7 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     size_t o_cf = add_array(parts, boff, ctu_frame);
     size_t o_if = add_array(parts, boff, item_frame);
     size_t o_units = add_array(parts, boff, units);
+    size_t o_briefs = add_array(parts, boff, briefs);
     size_t o_slots = add_array(parts, boff, slots);
     const size_t bytes = (boff + 255) & ~size_t(255);
     std::vector<char> host(bytes, 0);
@@ -555,6 +562,7 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     L.item_frame = reinterpret_cast<const int *>(bp + o_if);
     L.units = use_units ? reinterpret_cast<const trs::UnitDev *>(bp + o_units) : nullptr;
     L.slots = use_units ? reinterpret_cast<const trs::ChunkSlot *>(bp + o_slots) : nullptr;
+    L.briefs = use_units ? reinterpret_cast<const trs::ItemBrief *>(bp + o_briefs) : nullptr;
     L.n_units = (int)units.size();
     L.n_frames = n_frames;
     L.total_ctus = (int)ctu_frame.size();
@@ -571,6 +579,8 @@ trs_status trs_batch_create(const trs_batch_frame *frames, int32_t n_frames, int
     L.grid1 = (int)std::max<long long>(1, std::min<long long>(total_items, (long long)n_cu * occ1));
     L.grid2 = (int)std::max<long long>(1, std::min<long long>(total_items, (long long)n_cu * occ2));
     if (use_units) {
+        const int occ2u = wgs_per_cu ? wgs_per_cu : trs::step2_occupancy(L.block, rec_max, rid_max);
+        L.grid2 = (int)std::max<long long>(1, std::min<long long>(total_items, (long long)n_cu * occ2u));
         const int occu = wgs_per_cu ? wgs_per_cu : trs::unit_occupancy(L.block, rec_max, rid_max);
         L.grid_u = (int)std::max<long long>(1, std::min<long long>(L.n_units, (long long)n_cu * occu));
     }

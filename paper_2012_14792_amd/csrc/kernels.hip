@@ -968,7 +968,7 @@ __global__ void __launch_bounds__(BS)
 k_search_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restrict__ frames,
                const int *__restrict__ item_frame, int n_flat, char *ws,
                unsigned long long *__restrict__ item_min, Partial *__restrict__ part, int rec_max,
-               const int *__restrict__ live, const int *__restrict__ live_n)
+               const unsigned long long *__restrict__ live, const int *__restrict__ live_n)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds);
@@ -980,7 +980,7 @@ k_search_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restr
     int cur = -1;
     BatchFrameDev fr{};
     for (int x = beg; x < end; x++) {
-        const int g = P2 ? live[x] : x;
+        const int g = P2 ? frames[(int)(live[x] >> 32)].item_base + (int)(unsigned)live[x] : x;
         const int f = item_frame[g];
         if (f != cur) {
             fr = frames[f];
@@ -1005,12 +1005,12 @@ k_search_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restr
 }
 
 // One work-group per frame: T~min and the Eq. 4 bound from the frame's item minima; the
-// frame's items within the bound are appended (in item order, at a position reserved with
-// one atomic) to the step-2 list, and the others get an empty partial.
+// frame's items within the bound are appended as (frame << 32 | item), in item order at a
+// position reserved with one atomic, to the step-2 list, and the others get an empty partial.
 __global__ void __launch_bounds__(256)
 k_tmin_batch(const BatchFrameDev *__restrict__ frames,
              const unsigned long long *__restrict__ item_min, char *ws,
-             Partial *__restrict__ part, int *__restrict__ live, int *__restrict__ live_n)
+             Partial *__restrict__ part, unsigned long long *__restrict__ live, int *__restrict__ live_n)
 {
     constexpr int NW = 256 / kWave;
     __shared__ unsigned long long rt[NW];
@@ -1065,7 +1065,7 @@ k_tmin_batch(const BatchFrameDev *__restrict__ frames,
         __syncthreads();
         int off = base;
         for (int q = 0; q < wv; q++) off += wcnt[q];
-        if (ok) live[off + before] = fr.item_base + i;
+        if (ok) live[off + before] = ((unsigned long long)blockIdx.x << 32) | (unsigned)i;
         for (int q = 0; q < NW; q++) base += wcnt[q];
     }
 }
@@ -1217,6 +1217,113 @@ k_final_batch(const SpaceView *__restrict__ plans, const BatchFrameDev *__restri
                      fr.dt, fr.dr);
 }
 
+// Batched step 2 over the live list of (frame, item) entries, split evenly over the grid.
+// Per entry: the item's record indices go to LDS in 16-byte pieces; each thread builds
+// records from their compact descriptors with every corner load of the three SATs issued
+// before use (pixel sizes come from the CTU grid: a column boundary x sits at min(x cs, w));
+// lanes score candidates against the frame's Eq. 4 bound and keep the least (Q, T~, rank).
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_step2_live(const BatchFrameDev *__restrict__ frames, const ItemBrief *__restrict__ briefs,
+             const unsigned long long *__restrict__ live, const int *__restrict__ live_n, int cs,
+             int rec_max, char *ws, Partial *__restrict__ part)
+{
+    constexpr int NW = BS / kWave;
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned long long *recT = reinterpret_cast<unsigned long long *>(lds);
+    unsigned long long *recQ = recT + rec_max;
+    uint16_t *srid = reinterpret_cast<uint16_t *>(recQ + rec_max);
+    __shared__ unsigned long long redq[NW], redt[NW];
+    __shared__ long long redr[NW];
+    __shared__ int redf[NW];
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int total = *live_n;
+    const int G = gridDim.x, b = xcd_item(blockIdx.x, G);
+    const int beg = (int)((long long)total * b / G), end = (int)((long long)total * (b + 1) / G);
+    for (int x = beg; x < end; x++) {
+        const unsigned long long en = live[x];
+        const int f = (int)(en >> 32), i = (int)(unsigned)en;
+        const BatchFrameDev &fr = frames[f];
+        const ItemBrief ib = briefs[fr.brief_base + i];
+        const int n = ib.n_ent, T = ib.T, S = fr.W + 1, w = fr.w, h = fr.h;
+        const unsigned long long bound = reinterpret_cast<const WsHeader *>(ws + fr.o_hdr)->bound;
+        const gptr<long long> sT = as_global(reinterpret_cast<const long long *>(ws + fr.o_satT));
+        const gptr<long long> s1 = as_global(reinterpret_cast<const long long *>(ws + fr.o_satS1));
+        const gptr<long long> s2 = as_global(reinterpret_cast<const long long *>(ws + fr.o_satS2));
+        __syncthreads();                                // the previous entry's LDS is read
+        const gptr<u32x4> rsrc = as_global(reinterpret_cast<const u32x4 *>(ib.rids));
+        const int nv = (n * T + 7) >> 3;
+        u32x4 piece = {0u, 0u, 0u, 0u};
+        if (tid < nv) piece = rsrc[tid];
+        const gptr<u32x4> rd = as_global(reinterpret_cast<const u32x4 *>(ib.rdesc4));
+        for (int rid = tid; rid < ib.n_rec; rid += BS) {
+            const u32x4 d = rd[rid];
+            const int xa = d.x & 511, xb = (d.x >> 9) & 511, y0 = (int)(d.x >> 18);
+            const int k = d.y & 255;
+            const unsigned wpx = (unsigned)(min(xb * cs, w) - xa * cs);
+            unsigned long long tmax = 0, qs = 0;
+            int ya = y0;
+            for (int q = 0; q < k; q++) {
+                const int zi = q + 1;
+                const uint32_t wsel = zi < 4 ? d.y : zi < 8 ? d.z : d.w;
+                const int yb = y0 + (int)((wsel >> (8 * (zi & 3))) & 255);
+                const int i00 = ya * S + xa, i01 = ya * S + xb, i10 = yb * S + xa, i11 = yb * S + xb;
+                const long long t0 = sT[i11], t1 = sT[i01], t2 = sT[i10], t3 = sT[i00];
+                const long long a0 = s1[i11], a1 = s1[i01], a2 = s1[i10], a3 = s1[i00];
+                const long long b0 = s2[i11], b1 = s2[i01], b2 = s2[i10], b3 = s2[i00];
+                const unsigned hpx = (unsigned)(min(yb * cs, h) - ya * cs);
+                tmax = max(tmax, (unsigned long long)(t0 - t1 - t2 + t3));
+                qs += (unsigned long long)(b0 - b1 - b2 + b3) -
+                      floor_sq_div((unsigned long long)(a0 - a1 - a2 + a3), wpx * hpx);
+                ya = yb;
+            }
+            recT[rid] = tmax;
+            recQ[rid] = qs;
+        }
+        {
+            u32x4 *dst = reinterpret_cast<u32x4 *>(srid);
+            if (tid < nv) dst[tid] = piece;
+            for (int v = tid + BS; v < nv; v += BS) dst[v] = rsrc[v];
+        }
+        __syncthreads();
+        Key2 best{kNone, kNone, LLONG_MAX, -1};
+        for (int e = tid; e < n; e += BS) {
+            unsigned long long tmax = 0, qsum = 0;
+#pragma unroll 4
+            for (int t = 0; t < T; t++) {
+                const int rr = srid[t * n + e];
+                tmax = max(tmax, recT[rr]);
+                qsum += recQ[rr];
+            }
+            if (tmax <= bound && (qsum < best.q || (qsum == best.q && tmax <= best.t))) {
+                const int fe = (int)as_global(ib.ent_f)[e];
+                const int xl = fe / ib.M;
+                const Key2 cand{qsum, tmax, ib.rank0 + (long long)xl * ib.SM + (fe - xl * ib.M), fe};
+                if (key_less(cand, best)) best = cand;
+            }
+        }
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m >>= 1) {
+            Key2 o;
+            o.q = shfl_xor64(best.q, m);
+            o.t = shfl_xor64(best.t, m);
+            o.rank = (long long)shfl_xor64((unsigned long long)best.rank, m);
+            o.f = __shfl_xor(best.f, m, kWave);
+            if (key_less(o, best)) best = o;
+        }
+        if (lane == 0) { redq[wv] = best.q; redt[wv] = best.t; redr[wv] = best.rank; redf[wv] = best.f; }
+        __syncthreads();
+        if (tid == 0) {
+            Key2 bk{redq[0], redt[0], redr[0], redf[0]};
+            for (int q = 1; q < NW; q++) {
+                const Key2 o{redq[q], redt[q], redr[q], redf[q]};
+                if (key_less(o, bk)) bk = o;
+            }
+            part[fr.item_base + i] = Partial{bk.q, bk.t, bk.rank, i, bk.f, n, 0};
+        }
+    }
+}
+
 inline void mark(const hipEvent_t *ev, int i, hipStream_t s)
 {
     if (ev) (void)hipEventRecord(ev[i], s);
@@ -1227,7 +1334,7 @@ void launch_batch_search(const BatchLaunch &b, char *ws, hipStream_t s, const hi
 {
     auto *imin = reinterpret_cast<unsigned long long *>(ws + b.o_item_min);
     auto *part = reinterpret_cast<Partial *>(ws + b.o_part);
-    auto *live = reinterpret_cast<int *>(ws + b.o_live);
+    auto *live = reinterpret_cast<unsigned long long *>(ws + b.o_live);
     auto *live_n = reinterpret_cast<int *>(ws + b.o_live_n);
     if (b.units)
         hipLaunchKernelGGL(k_step1_units<BS>, dim3(b.grid_u), dim3(BS), unit_lds_bytes(b.rec_max, b.rid_max),
@@ -1240,9 +1347,13 @@ void launch_batch_search(const BatchLaunch &b, char *ws, hipStream_t s, const hi
     hipLaunchKernelGGL(k_tmin_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, imin, ws, part,
                        live, live_n);
     mark(ev, 4, s);
-    hipLaunchKernelGGL((k_search_batch<BS, true>), dim3(b.grid2), dim3(BS),
-                       batch_lds_bytes(b.rec_max, true), s, b.plans, b.frames, b.item_frame,
-                       b.total_items, ws, imin, part, b.rec_max, live, live_n);
+    if (b.briefs)
+        hipLaunchKernelGGL(k_step2_live<BS>, dim3(b.grid2), dim3(BS), step2_lds_bytes(b.rec_max, b.rid_max), s,
+                           b.frames, b.briefs, live, live_n, b.cs, b.rec_max, ws, part);
+    else
+        hipLaunchKernelGGL((k_search_batch<BS, true>), dim3(b.grid2), dim3(BS),
+                           batch_lds_bytes(b.rec_max, true), s, b.plans, b.frames, b.item_frame,
+                           b.total_items, ws, imin, part, b.rec_max, live, live_n);
 }
 
 template <int BS>
@@ -1264,6 +1375,25 @@ int unit_occupancy_of(int lds)
     return e == hipSuccess && n > 0 ? n : 1;
 }
 }  // namespace
+
+int step2_lds_bytes(int rec_max, int rid_max)
+{
+    return 16 * (rec_max > 0 ? rec_max : 1) + 2 * ((rid_max + 7) & ~7);
+}
+
+int step2_occupancy(int block, int rec_max, int rid_max)
+{
+    const int lds = step2_lds_bytes(rec_max, rid_max);
+    int n = 0;
+    hipError_t e;
+    switch (block) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2_live<64>, 64, lds); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2_live<128>, 128, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2_live<512>, 512, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2_live<256>, 256, lds); break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
+}
 
 int unit_lds_bytes(int rec_max, int rid_max)
 {
@@ -1426,7 +1556,8 @@ hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStre
         hipLaunchKernelGGL(k_tmin_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames,
                            reinterpret_cast<unsigned long long *>(ws + b.o_item_min), ws,
                            reinterpret_cast<Partial *>(ws + b.o_part),
-                           reinterpret_cast<int *>(ws + b.o_live), reinterpret_cast<int *>(ws + b.o_live_n));
+                           reinterpret_cast<unsigned long long *>(ws + b.o_live),
+                           reinterpret_cast<int *>(ws + b.o_live_n));
         mark(ev, 4, s);
     }
     mark(ev, 5, s);

@@ -55,6 +55,7 @@ struct BatchFrameDev {
     int w, h, W, H;
     int plan, lam_num, lam_den, dt;
     int dr, ctu_base, item_base, n_items;
+    int brief_base, pad1;             // first ItemBrief of this frame's plan
     long long o_s1, o_grad, o_tex, o_mean, o_var, o_s2, o_cost, o_hdr, o_satT, o_satS1, o_satS2;
 };
 
@@ -66,6 +67,14 @@ struct UnitDev {
     const uint32_t *rdesc4;           // the item's compact record descriptors
     int n_ent, n_rec, T, S;           // S = W + 1, the SAT row length
     int item, chunk, pad0, pad1;
+};
+// What the batched step 2 needs of one item of one plan (one load per live entry).
+struct ItemBrief {
+    const uint16_t *rids;             // record indices [T][n_ent], 16-byte aligned
+    const uint32_t *rdesc4;           // compact record descriptors
+    const uint32_t *ent_f;            // candidates' local indices
+    long long rank0, SM;              // rank = rank0 + (f / M) * SM + f % M
+    int n_ent, n_rec, T, M;
 };
 // One frame slot of a chunk: its SAT of predicted times (byte offset in the workspace) and
 // its first item in the flat item list (-1: empty slot, which reads the chunk's first frame).
@@ -80,17 +89,21 @@ struct BatchLaunch {
     const int *ctu_frame, *item_frame;
     const UnitDev *units;             // device; null: step 1 runs per (frame, item)
     const ChunkSlot *slots;           // device, kChunk per chunk
+    const ItemBrief *briefs;          // device, per (plan, item); null with units
     int n_frames, total_ctus, total_items, cs;
     int block, grid1, grid2, rec_max;
     int n_units, grid_u, rid_max, pad;
     long long o_item_min, o_part;     // byte offsets in the workspace
-    long long o_live, o_live_n;       // step-2 list of live (frame, item) entries and its length
+    long long o_live, o_live_n;       // step-2 list of live (frame << 32 | item) entries, its length
 };
 
 // Dynamic LDS of the frame-inner step-1 kernel, or 0 when the records and record indices
 // of the largest item do not fit.
 int unit_lds_bytes(int rec_max, int rid_max);
 int unit_occupancy(int block, int rec_max, int rid_max);
+// Dynamic LDS and occupancy of the batched step-2 kernel over the live list.
+int step2_lds_bytes(int rec_max, int rid_max);
+int step2_occupancy(int block, int rec_max, int rid_max);
 
 // Byte layout of one frame's region and its size (W x H CTUs).
 long long batch_frame_region(int W, int H, BatchFrameDev *fr, long long base);
