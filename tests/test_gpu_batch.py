@@ -156,3 +156,37 @@ def test_batch_profile_events(orc):
     assert torch.equal(batch.out, ref)
     assert B.trs_profile_read_batch() == ({k: 0.0 for k in B.BATCH_STAGES}, 0)
     batch.close()
+
+
+def test_batch_fallback_kernels_match_oracle(orc):
+    """A plan without compact record descriptors (one tile cut into 16 slices: k > 11) sends
+    the whole batch through the per-(frame, item) search kernels; the same frames without it
+    take the frame-inner kernels.  Both must give the per-frame launches' and the oracle's
+    results.  CTU 64 frames, so the CTU-size paths other than 128 run too."""
+    import torch
+    w, h = 1920, 1080
+    gen = synth.SequenceGenerator(w, h, 77, 8.0)
+    W, H = (w + 63) // 64, (h + 63) // 64
+    cases = [(16, 1, 1, 16, (1, 10)), (4, 3, 3, 2, (0, 1)), (8, 6, 4, 4, (1, 10)), (16, 1, 1, 16, (-1, 1))]
+    frames = []
+    for f, (N, C, R, K, lam) in enumerate(cases):
+        luma = gen.frame(f)
+        prev = synth.ctu_times(orc.features(gen.frame(f + 1), 64)["tex"], synth.ar1_eps(W * H, 1, 300 + f)[0])
+        frames.append(dict(width=w, height=h, ctu_size=64, luma_np=luma, prev_np=prev,
+                           params=B.make_params(N, C, R, K, lam=lam), luma=to_device(luma),
+                           prev=torch.from_numpy(prev.view(np.int32)).cuda()))
+    refs = [orc.partition(fr["luma_np"], fr["prev_np"], oracle_params(orc, fr["params"]), cs=64) for fr in frames]
+    for subset in (frames, frames[1:3]):
+        batch = B.Batch(subset)
+        batch.enqueue()
+        torch.cuda.synchronize()
+        got = batch.results()
+        for i, fr in enumerate(subset):
+            part = B.Partitioner(w, h, fr["params"], ctu_size=64)
+            single = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+            part.enqueue(fr["luma"], fr["prev"], out=single)
+            torch.cuda.synchronize()
+            assert torch.equal(single, batch.out[i]), f"frame {i} differs from its per-frame launch"
+            ref = refs[next(j for j, x in enumerate(frames) if x is fr)]
+            assert_same_result(got[i], ref, f"frame {i} of {len(subset)}")
+        batch.close()
