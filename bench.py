@@ -63,8 +63,8 @@ def main():
                     help="uhd_seq: the 64-frame 4K sequence; batch512: 512 mixed frames in one batch; "
                          "mlp: training steps of the learned CTU-time predictor")
     ap.add_argument("--mlp-batch", type=int, default=65536)
-    ap.add_argument("--split", type=int, default=0,
-                    help="batched form: sub-batches on their own streams (0: tuned, else 1)")
+    ap.add_argument("--pipeline", type=int, default=0,
+                    help="batched form: sub-batches pipelined over streams (0: tuned, else 1)")
     ap.add_argument("--form", default="batched", choices=["batched", "streams"],
                     help="4K sequence: one batched launch sequence per step, or per-frame launches "
                          "over --streams streams")
@@ -162,9 +162,10 @@ def main():
     tuned = (autotune.load(f"{autotune.arch()}|uhd_seq{F}") or {}) if not args.sched_block else {}
     block = args.sched_block or tuned.get("block", 0)
     wgs = args.wgs_per_cu or tuned.get("wgs_per_cu", 0)
-    # K sub-batches of consecutive frames, one stream each: one sub-batch's HBM-bound feature
-    # kernel can run beside another's latency-bound search kernels
-    K = max(1, min(F, args.split or tuned.get("split", 1)))
+    # K sub-batches of consecutive frames, one stream each.  Their feature launches run one
+    # after another (each waits for the previous one's), and each sub-batch's search follows
+    # its own features, so one sub-batch's search can overlap the next one's features.
+    K = max(1, min(F, args.pipeline or tuned.get("pipeline", 1)))
     cuts = [F * k // K for k in range(K + 1)]
     batches = [B.Batch([dict(width=w, height=h, params=params, luma=luma[f], prev=prev[f])
                         for f in range(cuts[k], cuts[k + 1])], block=block, wgs_per_cu=wgs) for k in range(K)]
@@ -177,8 +178,14 @@ def main():
         base = torch.cuda.current_stream()
         for st in bstreams:
             st.wait_stream(base)
+        done_features = None
         for bt, st in zip(batches, bstreams):
-            bt.enqueue(stream=st)
+            if done_features is not None:
+                st.wait_event(done_features)
+            bt.enqueue_features(stream=st)
+            done_features = torch.cuda.Event()
+            done_features.record(st)
+            bt.enqueue_search(stream=st)
         for st in bstreams:
             base.wait_stream(st)
 
@@ -325,8 +332,9 @@ def main():
                    "frames": F, "width": w, "height": h, "n_threads": 8,
                    "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
                    "form": args.form, "sub_batches": K if batched else None,
-                   "timing": (f"HIP graph of one step ({K} trs_batch_run over {F} frames, one stream each), "
-                              f"replayed once per step"
+                   "wgs_per_cu": wgs if batched else None,
+                   "timing": (f"HIP graph of one step ({K} batched runs over {F} frames, pipelined over "
+                              f"{K} streams), replayed once per step"
                               if batched else
                               f"HIP graph of one step ({F} trs_partition calls over {S} streams), replayed K times")},
         "candidates_scored_per_s": round(fps * stats["candidates"], 1),

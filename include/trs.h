@@ -209,6 +209,15 @@ trs_status trs_batch_workspace(trs_batch batch, size_t *bytes);
 trs_status trs_batch_run(trs_batch batch, void *workspace, size_t ws_bytes, trs_result *out_dev,
                          hipStream_t stream);
 
+/* trs_batch_run in two parts on the caller's streams: trs_batch_features enqueues the
+ * per-CTU features of every frame into the workspace (one launch); trs_batch_search enqueues
+ * the other five launches, which read them.  The caller orders the two (same stream, or an
+ * event); between them the features kernel of one batch can overlap another batch's search.
+ * Errors: as trs_batch_run. */
+trs_status trs_batch_features(trs_batch batch, void *workspace, size_t ws_bytes, hipStream_t stream);
+trs_status trs_batch_search(trs_batch batch, void *workspace, size_t ws_bytes, trs_result *out_dev,
+                            hipStream_t stream);
+
 /* Host: device pointers of frame `frame`'s per-CTU features and time map inside a batch
  * workspace (valid after trs_batch_run on that workspace).  Errors: TRS_EINVAL. */
 trs_status trs_batch_frame_arrays(trs_batch batch, void *workspace, int32_t frame,

@@ -138,6 +138,10 @@ def lib():
         L.trs_batch_workspace.restype = S
         L.trs_batch_run.argtypes = [P, P, ctypes.c_size_t, P, P]
         L.trs_batch_run.restype = S
+        L.trs_batch_features.argtypes = [P, P, ctypes.c_size_t, P]
+        L.trs_batch_features.restype = S
+        L.trs_batch_search.argtypes = [P, P, ctypes.c_size_t, P, P]
+        L.trs_batch_search.restype = S
         L.trs_batch_frame_arrays.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(Feat),
                                              ctypes.POINTER(ctypes.c_void_p)]
         L.trs_batch_frame_arrays.restype = S
@@ -415,6 +419,17 @@ class Batch:
     def enqueue(self, stream=None):
         check(lib().trs_batch_run(self._h, _ptr(self.ws), self.ws.numel(), _ptr(self.out), _stream(stream)),
               "trs_batch_run")
+        return self.out
+
+    def enqueue_features(self, stream=None):
+        """The feature launch of every frame (first part of enqueue)."""
+        check(lib().trs_batch_features(self._h, _ptr(self.ws), self.ws.numel(), _stream(stream)),
+              "trs_batch_features")
+
+    def enqueue_search(self, stream=None):
+        """The five launches after the features (second part of enqueue)."""
+        check(lib().trs_batch_search(self._h, _ptr(self.ws), self.ws.numel(), _ptr(self.out), _stream(stream)),
+              "trs_batch_search")
         return self.out
 
     def results(self) -> list:

@@ -46,7 +46,8 @@ thread_local FastPlan t_fast;
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<std::array<hipEvent_t, 4>> g_prof_events;
-std::vector<std::array<hipEvent_t, 7>> g_prof_batch;
+// Batch-run events and the launch stages they cover (trs::kStageFeatures / kStageSearch).
+std::vector<std::pair<std::array<hipEvent_t, 7>, int>> g_prof_batch;
 
 PlanKey plan_key(const trs_frame *f, const trs_search_params *p)
 {
@@ -233,6 +234,34 @@ struct trs_batch_s {
     std::vector<trs::BatchFrameDev> frames;
 };
 
+namespace {
+
+// The batch's launches for `stages`, with profiling events when enabled.
+trs_status batch_launch(trs_batch batch, void *workspace, size_t ws_bytes, trs_result *out_dev,
+                        hipStream_t stream, int stages)
+{
+    if (!batch) return TRS_EINVAL;
+    if (!workspace || ws_bytes < batch->ws_bytes || reinterpret_cast<uintptr_t>(workspace) % 256)
+        return TRS_EWORKSPACE;
+    std::array<hipEvent_t, 7> ev{};
+    bool prof = false;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (g_prof_on) {
+            for (auto &x : ev)
+                if (hipEventCreate(&x) != hipSuccess) return TRS_EDEVICE;
+            g_prof_batch.emplace_back(ev, stages);
+            prof = true;
+        }
+    }
+    return trs::launch_batch(batch->launch, static_cast<char *>(workspace), out_dev, stream,
+                             prof ? ev.data() : nullptr, stages) == hipSuccess
+               ? TRS_OK
+               : TRS_EDEVICE;
+}
+
+}  // namespace
+
 extern "C" {
 
 trs_status trs_features(const trs_frame *frame, const uint16_t *luma, int64_t stride_elems,
@@ -364,18 +393,22 @@ trs_status trs_profile_read_batch(double *ms, int64_t *runs)
     if (!ms || !runs) return TRS_EINVAL;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     trs_status st = TRS_OK;
+    int64_t n = 0;
     for (int k = 0; k < 6; k++) ms[k] = 0.0;
-    for (auto &ev : g_prof_batch) {
-        if (hipEventSynchronize(ev[6]) != hipSuccess) st = TRS_EDEVICE;
-        for (int k = 0; k < 6; k++) {
+    for (auto &rec : g_prof_batch) {
+        const auto &ev = rec.first;
+        const bool feat = rec.second & trs::kStageFeatures, srch = rec.second & trs::kStageSearch;
+        if (hipEventSynchronize(ev[srch ? 6 : 1]) != hipSuccess) st = TRS_EDEVICE;
+        for (int k = feat ? 0 : 1; k < (srch ? 6 : 1); k++) {
             float x = 0;
             if (hipEventElapsedTime(&x, ev[k], ev[k + 1]) != hipSuccess) st = TRS_EDEVICE;
             ms[k] += x;
         }
+        n += srch;
     }
-    *runs = (int64_t)g_prof_batch.size();
-    for (auto &ev : g_prof_batch)
-        for (auto &x : ev) (void)hipEventDestroy(x);
+    *runs = n;
+    for (auto &rec : g_prof_batch)
+        for (auto &x : rec.first) (void)hipEventDestroy(x);
     g_prof_batch.clear();
     return st;
 }
@@ -598,24 +631,20 @@ trs_status trs_batch_workspace(trs_batch batch, size_t *bytes)
 trs_status trs_batch_run(trs_batch batch, void *workspace, size_t ws_bytes, trs_result *out_dev,
                          hipStream_t stream)
 {
-    if (!batch || !out_dev) return TRS_EINVAL;
-    if (!workspace || ws_bytes < batch->ws_bytes || reinterpret_cast<uintptr_t>(workspace) % 256)
-        return TRS_EWORKSPACE;
-    std::array<hipEvent_t, 7> ev{};
-    bool prof = false;
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (g_prof_on) {
-            for (auto &x : ev)
-                if (hipEventCreate(&x) != hipSuccess) return TRS_EDEVICE;
-            g_prof_batch.push_back(ev);
-            prof = true;
-        }
-    }
-    return trs::launch_batch(batch->launch, static_cast<char *>(workspace), out_dev, stream,
-                             prof ? ev.data() : nullptr) == hipSuccess
-               ? TRS_OK
-               : TRS_EDEVICE;
+    if (!out_dev) return TRS_EINVAL;
+    return batch_launch(batch, workspace, ws_bytes, out_dev, stream, trs::kStageFeatures | trs::kStageSearch);
+}
+
+trs_status trs_batch_features(trs_batch batch, void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    return batch_launch(batch, workspace, ws_bytes, nullptr, stream, trs::kStageFeatures);
+}
+
+trs_status trs_batch_search(trs_batch batch, void *workspace, size_t ws_bytes, trs_result *out_dev,
+                            hipStream_t stream)
+{
+    if (!out_dev) return TRS_EINVAL;
+    return batch_launch(batch, workspace, ws_bytes, out_dev, stream, trs::kStageSearch);
 }
 
 trs_status trs_batch_frame_arrays(trs_batch batch, void *workspace, int32_t frame, trs_feat *feat,

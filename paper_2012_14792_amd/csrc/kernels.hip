@@ -1523,10 +1523,10 @@ int batch_occupancy(int block, int rec_max, bool step2)
 }
 
 hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s,
-                        const hipEvent_t *ev)
+                        const hipEvent_t *ev, int stages)
 {
     mark(ev, 0, s);
-    switch (b.cs) {
+    if (stages & kStageFeatures) switch (b.cs) {
     case 128:
         hipLaunchKernelGGL(k_features_batch<128>, dim3(b.total_ctus), dim3(256), 0, s, b.frames,
                            b.ctu_frame, ws);
@@ -1541,6 +1541,7 @@ hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStre
         break;
     }
     mark(ev, 1, s);
+    if (!(stages & kStageSearch)) return hipGetLastError();
     hipLaunchKernelGGL(k_cost_sat_batch, dim3(b.n_frames), dim3(256), 0, s, b.frames, ws,
                        reinterpret_cast<int *>(ws + b.o_live_n));
     mark(ev, 2, s);

@@ -110,9 +110,12 @@ long long batch_frame_region(int W, int H, BatchFrameDev *fr, long long base);
 int batch_lds_bytes(int rec_max, bool step2);
 // Work-groups per CU the batched search kernels can keep resident.
 int batch_occupancy(int block, int rec_max, bool step2);
-// ev (nullable): 7 events recorded before the first launch and after each of the six
+// stages: the feature launch, the five launches after it (cost map to result), or both.
+// ev (nullable, with both stages): 7 events recorded before the first launch and after each
+// of the six.
+constexpr int kStageFeatures = 1, kStageSearch = 2;
 hipError_t launch_batch(const BatchLaunch &b, char *ws, trs_result *out, hipStream_t s,
-                        const hipEvent_t *ev = nullptr);
+                        const hipEvent_t *ev = nullptr, int stages = kStageFeatures | kStageSearch);
 
 hipError_t launch_features(int w, int h, int cs, const uint16_t *luma, int64_t stride,
                            const trs_feat &out, hipStream_t s);

@@ -190,3 +190,59 @@ def test_batch_fallback_kernels_match_oracle(orc):
             ref = refs[next(j for j, x in enumerate(frames) if x is fr)]
             assert_same_result(got[i], ref, f"frame {i} of {len(subset)}")
         batch.close()
+
+
+def test_batch_split_calls_pipelined_over_streams(orc):
+    """trs_batch_features + trs_batch_search equal trs_batch_run, also when two batches are
+    pipelined over two streams (the second batch's features run beside the first's search),
+    eagerly and in a replayed graph; their profile events cover all six stages."""
+    import torch
+    frames = _mixed_frames(orc, SPEC[:4])
+    whole = B.Batch(frames)
+    whole.enqueue()
+    torch.cuda.synchronize()
+    halves = [B.Batch(frames[:2]), B.Batch(frames[2:])]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def step():
+        base = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(base)
+        ev = None
+        for bt, st in zip(halves, streams):
+            if ev is not None:
+                st.wait_event(ev)
+            bt.enqueue_features(stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+            bt.enqueue_search(stream=st)
+        for st in streams:
+            base.wait_stream(st)
+
+    B.trs_profile_read_batch()
+    B.trs_profile_enable(True)
+    try:
+        step()
+        torch.cuda.synchronize()
+    finally:
+        B.trs_profile_enable(False)
+    ms, runs = B.trs_profile_read_batch()
+    assert runs == 2 and all(v > 0 for v in ms.values())
+    assert torch.equal(torch.cat([h.out for h in halves]), whole.out)
+    for h in halves:
+        h.out.zero_()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap):
+            step()
+    torch.cuda.current_stream().wait_stream(cap)
+    for _ in range(3):
+        for h in halves:
+            h.out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(torch.cat([h.out for h in halves]), whole.out)
+    for bt in halves + [whole]:
+        bt.close()
