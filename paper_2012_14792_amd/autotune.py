@@ -146,7 +146,7 @@ def tune_per_frame(width, height, params, lumas, prevs, streams=8, reps=20,
     return {"best": best, "table": table}
 
 
-def tune_batch(items, reps=10, candidates=BATCH_CANDIDATES, log=print) -> dict:
+def tune_batch(items, reps=50, candidates=BATCH_CANDIDATES, log=print) -> dict:
     """Time the batched form under each (block, wgs_per_cu); results must not change."""
     import torch
 

@@ -1247,9 +1247,8 @@ k_step2_live(const BatchFrameDev *__restrict__ frames, const ItemBrief *__restri
         const ItemBrief ib = briefs[fr.brief_base + i];
         const int n = ib.n_ent, T = ib.T, S = fr.W + 1, w = fr.w, h = fr.h;
         const unsigned long long bound = reinterpret_cast<const WsHeader *>(ws + fr.o_hdr)->bound;
-        const gptr<long long> sT = as_global(reinterpret_cast<const long long *>(ws + fr.o_satT));
-        const gptr<long long> s1 = as_global(reinterpret_cast<const long long *>(ws + fr.o_satS1));
-        const gptr<long long> s2 = as_global(reinterpret_cast<const long long *>(ws + fr.o_satS2));
+        const gptr<char> sT = as_global(ws + fr.o_satT), s1 = as_global(ws + fr.o_satS1);
+        const gptr<char> s2 = as_global(ws + fr.o_satS2);
         __syncthreads();                                // the previous entry's LDS is read
         const gptr<u32x4> rsrc = as_global(reinterpret_cast<const u32x4 *>(ib.rids));
         const int nv = (n * T + 7) >> 3;
@@ -1262,19 +1261,24 @@ k_step2_live(const BatchFrameDev *__restrict__ frames, const ItemBrief *__restri
             const int k = d.y & 255;
             const unsigned wpx = (unsigned)(min(xb * cs, w) - xa * cs);
             unsigned long long tmax = 0, qs = 0;
+            auto at = [](gptr<char> base, unsigned o) { return *(const gptr<long long>)(base + o); };
+            // a slice's top corners are the previous slice's bottom corners
+            const unsigned p00 = 8u * (unsigned)(y0 * S + xa), p01 = 8u * (unsigned)(y0 * S + xb);
+            long long tt0 = at(sT, p00), tt1 = at(sT, p01), ta0 = at(s1, p00), ta1 = at(s1, p01);
+            long long tb0 = at(s2, p00), tb1 = at(s2, p01);
             int ya = y0;
             for (int q = 0; q < k; q++) {
                 const int zi = q + 1;
                 const uint32_t wsel = zi < 4 ? d.y : zi < 8 ? d.z : d.w;
                 const int yb = y0 + (int)((wsel >> (8 * (zi & 3))) & 255);
-                const int i00 = ya * S + xa, i01 = ya * S + xb, i10 = yb * S + xa, i11 = yb * S + xb;
-                const long long t0 = sT[i11], t1 = sT[i01], t2 = sT[i10], t3 = sT[i00];
-                const long long a0 = s1[i11], a1 = s1[i01], a2 = s1[i10], a3 = s1[i00];
-                const long long b0 = s2[i11], b1 = s2[i01], b2 = s2[i10], b3 = s2[i00];
+                const unsigned o10 = 8u * (unsigned)(yb * S + xa), o11 = 8u * (unsigned)(yb * S + xb);
+                const long long bt0 = at(sT, o10), bt1 = at(sT, o11), ba0 = at(s1, o10), ba1 = at(s1, o11);
+                const long long bb0 = at(s2, o10), bb1 = at(s2, o11);
                 const unsigned hpx = (unsigned)(min(yb * cs, h) - ya * cs);
-                tmax = max(tmax, (unsigned long long)(t0 - t1 - t2 + t3));
-                qs += (unsigned long long)(b0 - b1 - b2 + b3) -
-                      floor_sq_div((unsigned long long)(a0 - a1 - a2 + a3), wpx * hpx);
+                tmax = max(tmax, (unsigned long long)(bt1 - tt1 - bt0 + tt0));
+                qs += (unsigned long long)(bb1 - tb1 - bb0 + tb0) -
+                      floor_sq_div((unsigned long long)(ba1 - ta1 - ba0 + ta0), wpx * hpx);
+                tt0 = bt0; tt1 = bt1; ta0 = ba0; ta1 = ba1; tb0 = bb0; tb1 = bb1;
                 ya = yb;
             }
             recT[rid] = tmax;
