@@ -312,8 +312,9 @@ k_sat(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__restric
     }
 }
 
-// The same tables for grids with (H+1)(W+1) <= kSatLds: one thread per CTU row keeps
-// running sums in registers (rows are short), then one thread per column, through LDS.
+// The same tables for grids with (H+1)(W+1) <= kSatLds, by one work-group: the inputs are
+// read into LDS by every thread at once (at entry (y + 1, x + 1) of the tables' layout), then
+// one thread per CTU row and one per column keep running sums in LDS.
 constexpr int kSatLds = 2304;
 
 __global__ void __launch_bounds__(256)
@@ -322,24 +323,32 @@ k_sat_lds(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__res
           long long *satS2, WsHeader *hdr)
 {
     __shared__ long long lT[kSatLds], l1[kSatLds], l2[kSatLds];
-    const int tid = threadIdx.x;
-    const int S = W + 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int S = W + 1, n = W * H;
     (void)hdr;
-    for (int y = tid; y < H; y += blockDim.x) {
+    for (int i = tid; i < n; i += nt) {
+        const int y = i / W, e = (y + 1) * S + (i - y * W) + 1;
+        lT[e] = cost[i];
+        l1[e] = s1[i];
+        l2[e] = (long long)s2[i];
+    }
+    for (int y = tid; y <= H; y += nt) lT[y * S] = l1[y * S] = l2[y * S] = 0;
+    for (int x = tid; x <= W; x += nt) lT[x] = l1[x] = l2[x] = 0;
+    __syncthreads();
+    for (int y = tid; y < H; y += nt) {
         long long aT = 0, a1 = 0, a2 = 0;
-        const int e0 = (y + 1) * S;
-        lT[e0] = l1[e0] = l2[e0] = 0;
+        const int e0 = (y + 1) * S + 1;
         for (int x = 0; x < W; x++) {
-            aT += cost[y * W + x];
-            a1 += s1[y * W + x];
-            a2 += (long long)s2[y * W + x];
-            lT[e0 + x + 1] = aT;
-            l1[e0 + x + 1] = a1;
-            l2[e0 + x + 1] = a2;
+            aT += lT[e0 + x];
+            a1 += l1[e0 + x];
+            a2 += l2[e0 + x];
+            lT[e0 + x] = aT;
+            l1[e0 + x] = a1;
+            l2[e0 + x] = a2;
         }
     }
     __syncthreads();
-    for (int x = tid; x <= W; x += blockDim.x) {
+    for (int x = tid; x <= W; x += nt) {
         long long aT = 0, a1 = 0, a2 = 0;
         satT[x] = satS1[x] = satS2[x] = 0;
         for (int y = 1; y <= H; y++) {
@@ -353,7 +362,9 @@ k_sat_lds(int W, int H, const uint32_t *__restrict__ cost, const uint32_t *__res
     }
 }
 
-// Cost map fused with the LDS prefix sums (same grids as k_sat_lds), by one work-group.
+// Cost map fused with the LDS prefix sums (same grids as k_sat_lds), by one work-group.  All
+// inputs are first read into LDS by every thread at once (in the tables' layout, at entry
+// (y + 1, x + 1)), so the serial row and column sums touch LDS only.
 __device__ void cost_sat_body(int W, int H, const uint32_t *__restrict__ tex,
                               const uint32_t *__restrict__ prev, uint32_t a, uint32_t b,
                               uint32_t wp, uint32_t *__restrict__ cost, uint32_t *flags,
@@ -362,34 +373,37 @@ __device__ void cost_sat_body(int W, int H, const uint32_t *__restrict__ tex,
                               long long *satS1, long long *satS2)
 {
     __shared__ long long lT[kSatLds], l1[kSatLds], l2[kSatLds];
-    __shared__ uint32_t lc[kSatLds];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int S = W + 1, n = W * H;
     bool any_over = false;
     for (int i = tid; i < n; i += nt) {
         bool over;
         const uint32_t v = cost_of(tex[i], prev, i, a, b, wp, &over);
+        const int y = i / W, e = (y + 1) * S + (i - y * W) + 1;
         cost[i] = v;
-        lc[i] = v;
+        lT[e] = v;
+        l1[e] = s1[i];
+        l2[e] = (long long)s2[i];
         any_over |= over;
     }
     if (any_over && flags) atomicOr(flags, 1u);
+    for (int y = tid; y <= H; y += nt) lT[y * S] = l1[y * S] = l2[y * S] = 0;
+    for (int x = tid; x <= W; x += nt) lT[x] = l1[x] = l2[x] = 0;
     __syncthreads();
-    for (int y = tid; y < H; y += nt) {
+    for (int y = tid; y < H; y += nt) {                 // row sums in place
         long long aT = 0, a1 = 0, a2 = 0;
-        const int e0 = (y + 1) * S;
-        lT[e0] = l1[e0] = l2[e0] = 0;
+        const int e0 = (y + 1) * S + 1;
         for (int x = 0; x < W; x++) {
-            aT += lc[y * W + x];
-            a1 += s1[y * W + x];
-            a2 += (long long)s2[y * W + x];
-            lT[e0 + x + 1] = aT;
-            l1[e0 + x + 1] = a1;
-            l2[e0 + x + 1] = a2;
+            aT += lT[e0 + x];
+            a1 += l1[e0 + x];
+            a2 += l2[e0 + x];
+            lT[e0 + x] = aT;
+            l1[e0 + x] = a1;
+            l2[e0 + x] = a2;
         }
     }
     __syncthreads();
-    for (int x = tid; x <= W; x += nt) {
+    for (int x = tid; x <= W; x += nt) {                // column sums, written out
         long long aT = 0, a1 = 0, a2 = 0;
         satT[x] = satS1[x] = satS2[x] = 0;
         for (int y = 1; y <= H; y++) {
@@ -1012,7 +1026,7 @@ k_tmin_batch(const BatchFrameDev *__restrict__ frames,
              const unsigned long long *__restrict__ item_min, char *ws,
              Partial *__restrict__ part, unsigned long long *__restrict__ live, int *__restrict__ live_n)
 {
-    constexpr int NW = 256 / kWave;
+    constexpr int NW = 256 / kWave, KR = 8;           // items per thread held in registers
     __shared__ unsigned long long rt[NW];
     __shared__ unsigned long long sbound;
     __shared__ int wcnt[NW];
@@ -1020,9 +1034,15 @@ k_tmin_batch(const BatchFrameDev *__restrict__ frames,
     const BatchFrameDev fr = frames[blockIdx.x];
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const unsigned long long *im = item_min + fr.item_base;
+    const int n = fr.n_items;
+    // item tid + 256 q of each 2048-item block; the first block stays in registers
+    unsigned long long v[KR];
+#pragma unroll
+    for (int q = 0; q < KR; q++) v[q] = tid + 256 * q < n ? im[tid + 256 * q] : kNone;
     unsigned long long t = kNone;
-    int cnt = 0;
-    for (int i = tid; i < fr.n_items; i += 256) t = min(t, im[i]);
+#pragma unroll
+    for (int q = 0; q < KR; q++) t = min(t, v[q]);
+    for (int i = tid + 256 * KR; i < n; i += 256) t = min(t, im[i]);
 #pragma unroll
     for (int m = kWave / 2; m >= 1; m >>= 1) t = min(t, shfl_xor64(t, m));
     if (lane == 0) rt[wv] = t;
@@ -1040,23 +1060,31 @@ k_tmin_batch(const BatchFrameDev *__restrict__ frames,
     }
     __syncthreads();
     const unsigned long long bound = sbound;
-    for (int i = tid; i < fr.n_items; i += 256) cnt += im[i] <= bound;
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < KR; q++) cnt += tid + 256 * q < n && v[q] <= bound;
+    for (int i = tid + 256 * KR; i < n; i += 256) cnt += im[i] <= bound;
 #pragma unroll
     for (int m = kWave / 2; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, kWave);
     if (lane == 0) wcnt[wv] = cnt;
     __syncthreads();
     if (tid == 0) {
-        int n = 0;
-        for (int i = 0; i < NW; i++) n += wcnt[i];
-        hdr->n_live = n;
-        sbase = n ? atomicAdd(live_n, n) : 0;
+        int c = 0;
+        for (int i = 0; i < NW; i++) c += wcnt[i];
+        hdr->n_live = c;
+        sbase = c ? atomicAdd(live_n, c) : 0;
     }
     __syncthreads();
     int base = sbase;
-    for (int i0 = 0; i0 < fr.n_items; i0 += 256) {
-        const int i = i0 + tid;
-        const bool in = i < fr.n_items;
-        const bool ok = in && im[i] <= bound;
+    for (int i0 = 0; i0 < n; i0 += 256) {
+        const int i = i0 + tid, q = i0 / 256;
+        const bool in = i < n;
+        unsigned long long val = kNone;
+#pragma unroll
+        for (int r = 0; r < KR; r++)
+            if (r == q) val = v[r];
+        if (q >= KR && in) val = im[i];
+        const bool ok = in && val <= bound;
         if (in && !ok) part[fr.item_base + i] = Partial{kNone, kNone, LLONG_MAX, i, -1, 0, 0};
         const unsigned long long mask = __ballot(ok);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
@@ -1064,9 +1092,9 @@ k_tmin_batch(const BatchFrameDev *__restrict__ frames,
         if (lane == 0) wcnt[wv] = __popcll(mask);
         __syncthreads();
         int off = base;
-        for (int q = 0; q < wv; q++) off += wcnt[q];
+        for (int w = 0; w < wv; w++) off += wcnt[w];
         if (ok) live[off + before] = ((unsigned long long)blockIdx.x << 32) | (unsigned)i;
-        for (int q = 0; q < NW; q++) base += wcnt[q];
+        for (int w = 0; w < NW; w++) base += wcnt[w];
     }
 }
 
