@@ -579,7 +579,7 @@ def run_mlp(args):
     T = torch.rand(pool, generator=g, device="cuda") * 3
     m = TimeMLP(seed=0)
     m.fit_norm(X)
-    opt = torch.optim.Adam(m.parameters(), lr=1e-3)
+    opt = torch.optim.Adam(m.parameters(), lr=1e-3, fused=True)
     idx = [torch.randint(0, pool, (nb,), generator=g, device="cuda") for _ in range(16)]
     xs = [X[i].contiguous() for i in idx]
     ts = [T[i].contiguous() for i in idx]

@@ -3,8 +3,8 @@
 // conclusion names a better CTU time estimator as future work).
 //
 //   k_mlp_inputs      the 10 raw inputs per CTU from the method's own features and times
-//   k_mlp_fwd         one sample per lane, weights in LDS; optionally keeps z1, z2
-//   k_mlp_bwd_data    per-sample dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1)
+//   k_mlp_fwd         two lanes per sample, weights in LDS; optionally keeps z1, z2
+//   k_mlp_bwd_data    per sample (two lanes) dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1)
 //   k_mlp_bwd_w       weight gradients: each work-group sums its sample chunk into one
 //                     partial (entries spread over threads, samples staged in LDS tiles)
 //   k_mlp_reduce      partials summed in a fixed order, one wave per entry (deterministic)
@@ -71,6 +71,16 @@ k_mlp_inputs(int W, int H, int cs, int w, int h, const uint32_t *__restrict__ te
     o[9] = n / (float)(cs * cs);
 }
 
+// Lanes 2i and 2i + 1 work on one sample: pair_swap returns the partner lane's value.
+__device__ __forceinline__ float pair_swap(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF,
+                                                                 0xF, false));   // quad_perm 1,0,3,2
+}
+
+// Two lanes per sample: both evaluate the first layer; the lane of half hf takes the second
+// layer's outputs 32 hf .. 32 hf + 31 and its share of the output sum, and the pair adds the
+// two shares (half 0's first, so every lane forms the same sum).
 __global__ void __launch_bounds__(256)
 k_mlp_fwd(Weights wt, trs_mlp_norm nm, const float *__restrict__ x, long long n,
           float *__restrict__ y, float *__restrict__ z1o, float *__restrict__ z2o)
@@ -78,31 +88,39 @@ k_mlp_fwd(Weights wt, trs_mlp_norm nm, const float *__restrict__ x, long long n,
     __shared__ float sW1[kHid * kIn], sb1[kHid], sW2[kHid * kHid], sb2[kHid], sW3[kHid], sb3[1];
     load_weights(wt, sW1, sb1, sW2, sb2, sW3, sb3);
     __syncthreads();
-    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long s = g >> 1;
+    const int hf = (int)(g & 1);
+    const bool ok = s < n;                     // both lanes of a pair agree
+    const long long sc = ok ? s : 0;
     float xn[kIn];
 #pragma unroll
-    for (int i = 0; i < kIn; i++) xn[i] = (x[s * kIn + i] - nm.mean[i]) * nm.inv_std[i];
+    for (int i = 0; i < kIn; i++) xn[i] = (x[sc * kIn + i] - nm.mean[i]) * nm.inv_std[i];
     float h1[kHid];
 #pragma unroll
     for (int j = 0; j < kHid; j++) {
         float z = sb1[j];
 #pragma unroll
         for (int i = 0; i < kIn; i++) z = fmaf(sW1[j * kIn + i], xn[i], z);
-        if (z1o) z1o[(long long)j * n + s] = z;
+        if (z1o && ok && (j >> 5) == hf) z1o[(long long)j * n + s] = z;
         h1[j] = gelu(z);
     }
-    float out = sb3[0];
-    for (int k = 0; k < kHid; k++) {
+    float part = 0.0f;
+    for (int kk = 0; kk < kHid / 2; kk++) {
+        const int k = (kHid / 2) * hf + kk;
         float z = sb2[k];
 #pragma unroll
         for (int j = 0; j < kHid; j++) z = fmaf(sW2[k * kHid + j], h1[j], z);
-        if (z2o) z2o[(long long)k * n + s] = z;
-        out = fmaf(sW3[k], gelu(z), out);
+        if (z2o && ok) z2o[(long long)k * n + s] = z;
+        part = fmaf(sW3[k], gelu(z), part);
     }
-    y[s] = out;
+    const float other = pair_swap(part);
+    if (ok && hf == 0) y[s] = sb3[0] + (part + other);
 }
 
+// Two lanes per sample: the lane of half hf owns dz2 for k in 32 hf .. 32 hf + 31, forms its
+// share of W2^T dz2 for every j, and the pair adds the shares (half 0's first); each lane then
+// writes dz1 for its half of j.
 __global__ void __launch_bounds__(256)
 k_mlp_bwd_data(Weights wt, const float *__restrict__ z1, const float *__restrict__ z2,
                const float *__restrict__ dy, long long n, float *__restrict__ dz1o,
@@ -111,20 +129,27 @@ k_mlp_bwd_data(Weights wt, const float *__restrict__ z1, const float *__restrict
     __shared__ float sW1[kHid * kIn], sb1[kHid], sW2[kHid * kHid], sb2[kHid], sW3[kHid], sb3[1];
     load_weights(wt, sW1, sb1, sW2, sb2, sW3, sb3);
     __syncthreads();
-    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const float g = dy[s];
-    float dz2[kHid];
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long s = g >> 1;
+    const int hf = (int)(g & 1);
+    const bool ok = s < n;
+    const long long sc = ok ? s : 0;
+    const float gy = dy[sc];
+    constexpr int KH = kHid / 2;
+    float dz2[KH];
 #pragma unroll
-    for (int k = 0; k < kHid; k++) {
-        dz2[k] = g * sW3[k] * gelu_grad(z2[(long long)k * n + s]);
-        dz2o[(long long)k * n + s] = dz2[k];
+    for (int kk = 0; kk < KH; kk++) {
+        const int k = KH * hf + kk;
+        dz2[kk] = gy * sW3[k] * gelu_grad(z2[(long long)k * n + sc]);
+        if (ok) dz2o[(long long)k * n + s] = dz2[kk];
     }
     for (int j = 0; j < kHid; j++) {
         float a = 0.0f;
 #pragma unroll
-        for (int k = 0; k < kHid; k++) a = fmaf(sW2[k * kHid + j], dz2[k], a);
-        dz1o[(long long)j * n + s] = a * gelu_grad(z1[(long long)j * n + s]);
+        for (int kk = 0; kk < KH; kk++) a = fmaf(sW2[(KH * hf + kk) * kHid + j], dz2[kk], a);
+        const float o = pair_swap(a);
+        const float tot = hf == 0 ? a + o : o + a;
+        if (ok && (j >> 5) == hf) dz1o[(long long)j * n + s] = tot * gelu_grad(z1[(long long)j * n + s]);
     }
 }
 
@@ -292,7 +317,7 @@ hipError_t launch_mlp_forward(const trs_mlp &m, const trs_mlp_norm &nm, const fl
                               float *y, float *z1, float *z2, hipStream_t s)
 {
     const Weights w{m.w1, m.b1, m.w2, m.b2, m.w3, m.b3};
-    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, nm, x, n, y,
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, w, nm, x, n, y,
                        z1, z2);
     return hipGetLastError();
 }
@@ -322,7 +347,7 @@ hipError_t launch_mlp_backward(const trs_mlp &m, const trs_mlp_norm &nm, const f
     float *part = dz2 + kHid * n;
     const long long chunk = mlp_chunk(n);
     const int parts = (int)((n + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_mlp_bwd_data, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, z1, z2,
+    hipLaunchKernelGGL(k_mlp_bwd_data, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, w, z1, z2,
                        dy, n, dz1, dz2);
     hipLaunchKernelGGL(k_mlp_bwd_w, dim3(parts), dim3(256), 0, s, nm, x, z1, z2, dz1, dz2, dy, n,
                        (int)chunk, part);

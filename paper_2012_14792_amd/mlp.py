@@ -94,7 +94,7 @@ class TimeMLP:
         """Adam on the mean squared error of the predicted times (milliseconds), with the
         learning rate decayed to zero on a cosine over all steps.  Returns the mean training
         loss of each epoch."""
-        opt = torch.optim.Adam(self.parameters(), lr=lr)
+        opt = torch.optim.Adam(self.parameters(), lr=lr, fused=X.is_cuda)
         n = X.shape[0]
         per_epoch = (n + batch - 1) // batch
         total = max(1, epochs * per_epoch)
