@@ -63,6 +63,8 @@ def main():
                     help="uhd_seq: the 64-frame 4K sequence; batch512: 512 mixed frames in one batch; "
                          "mlp: training steps of the learned CTU-time predictor")
     ap.add_argument("--mlp-batch", type=int, default=65536)
+    ap.add_argument("--prune", type=int, default=0,
+                    help="optional pruning rules (bit 0: slice heights, bit 1: mean areas); 0 = the paper's method")
     ap.add_argument("--pipeline", type=int, default=0,
                     help="batched form: sub-batches pipelined over streams (0: tuned, else 1)")
     ap.add_argument("--form", default="batched", choices=["batched", "streams"],
@@ -96,7 +98,7 @@ def main():
     torch.cuda.set_device(0)
     params = B.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
                            cfg["max_rs_per_tile"], lam=cfg["lam"], sched_block=args.sched_block,
-                           sched_item=args.sched_item)
+                           sched_item=args.sched_item, prune=args.prune)
     if not (args.sched_block or args.sched_item):
         params = autotune.tuned_params(w, h, params)       # cached schedule, if any
     frame = B.make_frame(w, h)
@@ -289,7 +291,7 @@ def main():
         cores = min(len(os.sched_getaffinity(0)), args.cpu_threads)
         n_cpu = min(F, args.cpu_frames or 4 * cores)
         oparams = oracle.make_params(cfg["n_threads"], cfg["max_tile_cols"], cfg["max_tile_rows"],
-                                     cfg["max_rs_per_tile"], lam=cfg["lam"])
+                                     cfg["max_rs_per_tile"], lam=cfg["lam"], prune=args.prune)
         otex = [oracle.features(frames[f])["tex"] for f in range(n_cpu)]
         oprev = [synth.ctu_times(otex[max(f - 1, 0)], eps[max(f - 1, 0)]) for f in range(n_cpu)]
         log(f"cpu baseline: oracle on {n_cpu} frames with {cores} threads")
@@ -331,7 +333,7 @@ def main():
                                f"{stats['candidates']} candidates/frame ({stats['feasible']} area-feasible)",
                    "frames": F, "width": w, "height": h, "n_threads": 8,
                    "candidates_per_frame": stats["candidates"], "work_items": stats["items"],
-                   "form": args.form, "sub_batches": K if batched else None,
+                   "form": args.form, "sub_batches": K if batched else None, "prune": args.prune,
                    "wgs_per_cu": wgs if batched else None,
                    "timing": (f"HIP graph of one step ({K} batched runs over {F} frames, pipelined over "
                               f"{K} streams), replayed once per step"

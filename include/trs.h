@@ -91,12 +91,21 @@ typedef struct trs_blend {
  *   space_budget    ladder budget, <= 0 means 2^24;
  *   sched_block     work-group size for the search kernels (64, 128, 256, 512; 0 = 256);
  *   sched_item      target area-feasible candidates per work item (0 = 512).  The schedule
- *                   changes speed only, never the result. */
+ *                   changes speed only, never the result;
+ *   prune           extra geometric rules, off by default (0), from the authors' pruning notes
+ *                   left as comments in the paper's source: bit 0 (TRS_PRUNE_HEIGHTS) drops a
+ *                   candidate with a tile whose largest slice height (pixels) exceeds twice its
+ *                   smallest; bit 1 (TRS_PRUNE_MEANS) drops a candidate with a tile whose mean
+ *                   slice area is above 1.5 times, or below 1/1.5 of, the mean area of the other
+ *                   tiles' slices.  Like the area rule, they apply in both steps. */
+#define TRS_PRUNE_HEIGHTS 1
+#define TRS_PRUNE_MEANS 2
 typedef struct trs_search_params {
     int32_t n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile;
     int32_t area_k, lambda_num, lambda_den;
     int32_t dtile, drs;
     int32_t sched_block, sched_item;
+    int32_t prune;
     int64_t space_budget;
 } trs_search_params;
 

@@ -93,8 +93,35 @@ def regions_of(W, H, cand):
     return rs
 
 
+def coherent(cand, rs, area, row_px, N, prune):
+    """The authors' commented pruning notes as rules (pixel units): bit 0, the tallest slice of
+    every tile is at most twice its shortest; bit 1, every tile's mean slice area is within
+    [1/1.5, 1.5] times the mean slice area of the other tiles (when they hold any slice)."""
+    if not prune:
+        return True
+    choice = cand[4]
+    tiles, pos = [], 0
+    for k, _ in choice:
+        tiles.append(rs[pos:pos + k])
+        pos += k
+    heights = [[sum(row_px[y] for y in range(q[1], q[3])) for q in t] for t in tiles]
+    if prune & 1 and any(max(hs) > 2 * min(hs) for hs in heights):
+        return False
+    if prune & 2:
+        tile_area = [sum(area(q) for q in t) for t in tiles]
+        total = sum(tile_area)
+        for t, a in zip(tiles, tile_area):
+            k, rest = len(t), N - len(t)
+            if rest <= 0:
+                continue
+            mean_cur, mean_rem = Fraction(a, k), Fraction(total - a, rest)
+            if mean_cur > Fraction(3, 2) * mean_rem or mean_cur < mean_rem / Fraction(3, 2):
+                return False
+    return True
+
+
 def brute_search(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3,
-                 dt=None, dr=None):
+                 dt=None, dr=None, prune=0):
     """Returns dict(rank, t_min, t_sel, q_sel, rs, n_enumerated, n_feasible).
 
     `cost` is the per-CTU time map (raster, length W*H); lam is a Fraction or None (= inf).
@@ -103,6 +130,7 @@ def brute_search(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3,
     W, H = (w + cs - 1) // cs, (h + cs - 1) // cs
     n, s1, s2, _ = ctu_stats_pixels(luma, cs)
     T = [[int(cost[y * W + x]) for x in range(W)] for y in range(H)]
+    row_px = [min(cs, h - y * cs) for y in range(H)]
     cands = enumerate_candidates(W, H, N, Cmax, Rmax, Kmax, dt, dr)
 
     def rsum(a, rect):
@@ -113,7 +141,8 @@ def brute_search(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3,
     for rank, cand in enumerate(cands):
         rs = regions_of(W, H, cand)
         areas = [rsum(n, q) for q in rs]
-        feasible = area_k == 0 or area_k * min(areas) > max(areas)
+        feasible = (area_k == 0 or area_k * min(areas) > max(areas)) and \
+            coherent(cand, rs, lambda q: rsum(n, q), row_px, N, prune)
         t = max(rsum(T, q) for q in rs)
         qv = sum(rsum(s2, q) - (rsum(s1, q) ** 2) // rsum(n, q) for q in rs)
         scored.append((rank, feasible, t, qv, rs))

@@ -56,6 +56,7 @@ typedef struct {
 typedef struct {
     int32_t n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile, area_k;
     int32_t lambda_num, lambda_den, dtile, drs;
+    int32_t prune;          /* bit 0: slice heights within 2x in a tile; bit 1: tile mean areas */
     int64_t space_budget;
 } orc_params;
 
@@ -294,7 +295,7 @@ int orc_space_size(int W, int H, const orc_params *p, int64_t *n, int32_t *dt, i
 
 typedef struct {
     /* geometry */
-    int W, H, N, Km, karea, cs;
+    int W, H, N, Km, karea, cs, prune;
     int64_t *colpx, *rowpx;                /* pixel prefix: colpx[x] = width of CTU cols < x */
     int64_t *satT, *satS1, *satS2;         /* (H+1) x (W+1) inclusive prefix sums */
     int64_t lam_num, lam_den;
@@ -348,6 +349,41 @@ static int is_uniform(const search_ctx *s)
     return 1;
 }
 
+/* The authors' commented pruning notes, taken literally as geometric rules on the current
+ * candidate (pixel units, as the area rule):
+ *   heights: in every tile, the tallest slice is at most twice the shortest;
+ *   means:   in every tile, mean slice area = tile area / k lies within [1/1.5, 1.5] times the
+ *            mean slice area over the other tiles (other area / (N - k)), when N > k.
+ * Returns 1 when the candidate passes the rules selected by s->prune. */
+static int coherent(const search_ctx *s)
+{
+    if (!s->prune) return 1;
+    int64_t total = 0, tarea[ORC_MAXN];
+    for (int j = 0; j < s->r; j++)
+        for (int i = 0; i < s->c; i++) {
+            const int t = j * s->c + i;
+            const int64_t wpx = s->colpx[s->X[i + 1]] - s->colpx[s->X[i]];
+            int64_t hmin = INT64_MAX, hmax = 0;
+            for (int q = 0; q < s->k[t]; q++) {
+                const int64_t h = s->rowpx[s->Y[j] + s->Z[t][q + 1]] - s->rowpx[s->Y[j] + s->Z[t][q]];
+                if (h < hmin) hmin = h;
+                if (h > hmax) hmax = h;
+            }
+            if ((s->prune & 1) && hmax > 2 * hmin) return 0;
+            tarea[t] = wpx * (s->rowpx[s->Y[j + 1]] - s->rowpx[s->Y[j]]);
+            total += tarea[t];
+        }
+    if (s->prune & 2)
+        for (int t = 0; t < s->c * s->r; t++) {
+            const int64_t k = s->k[t], rest = s->N - k;
+            if (rest <= 0) continue;
+            const int64_t a = tarea[t], o = total - tarea[t];
+            /* a / k > 1.5 o / rest  or  a / k < o / (1.5 rest) */
+            if (2 * a * rest > 3 * o * k || 3 * a * rest < 2 * o * k) return 0;
+        }
+    return 1;
+}
+
 static void evaluate(search_ctx *s)
 {
     int rs[ORC_MAXN][4];
@@ -359,7 +395,7 @@ static void evaluate(search_ctx *s)
         if (A > amax) amax = A;
     }
     if (s->pass == 1 && is_uniform(s)) s->uniform_rank = s->rank;
-    int feasible = (s->karea == 0) || ((int64_t)s->karea * amin > amax);
+    int feasible = ((s->karea == 0) || ((int64_t)s->karea * amin > amax)) && coherent(s);
     if (feasible) {
         for (int q = 0; q < n; q++) {
             int64_t T = rect_sum(s->satT, s->W, rs[q][0], rs[q][1], rs[q][2], rs[q][3]);
@@ -503,7 +539,8 @@ int orc_search(int w, int h, int cs, const orc_params *p, const uint32_t *cost,
     if (w <= 0 || h <= 0 || cs <= 0) return -1;
     int W = (w + cs - 1) / cs, H = (h + cs - 1) / cs;
     if (p->n_threads < 1 || p->n_threads > ORC_MAXN || p->max_tile_cols < 1 || p->max_tile_rows < 1 ||
-        p->max_rs_per_tile < 1 || p->lambda_den < 1 || p->area_k < 0) return -1;
+        p->max_rs_per_tile < 1 || p->lambda_den < 1 || p->area_k < 0 || p->prune < 0 || p->prune > 3)
+        return -1;
     int64_t n_space; int32_t dt, dr;
     if (orc_space_size(W, H, p, &n_space, &dt, &dr) != 0) return -1;
     if (n_space <= 0 || n_space > ((int64_t)1 << 40)) return -3;
@@ -511,6 +548,7 @@ int orc_search(int w, int h, int cs, const orc_params *p, const uint32_t *cost,
     search_ctx s;
     memset(&s, 0, sizeof(s));
     s.W = W; s.H = H; s.N = p->n_threads; s.Km = p->max_rs_per_tile; s.karea = p->area_k; s.cs = cs;
+    s.prune = p->prune;
     s.dr = dr;
     s.lam_num = p->lambda_num; s.lam_den = p->lambda_den;
     s.colpx = calloc((size_t)W + 1, sizeof(int64_t));

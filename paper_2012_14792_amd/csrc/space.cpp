@@ -165,6 +165,7 @@ trs_status check_space_args(const trs_frame *f, const trs_search_params *p)
     if (p->max_tile_cols < 1 || p->max_tile_rows < 1 || p->max_rs_per_tile < 1) return TRS_EINVAL;
     if (p->max_tile_cols > kMaxRS || p->max_tile_rows > kMaxRS) return TRS_EINVAL;
     if (p->area_k < 0 || p->area_k > 1000000) return TRS_EINVAL;
+    if (p->prune < 0 || p->prune > 3) return TRS_EINVAL;
     if (p->lambda_den < 1 || p->lambda_den > 65535 || p->lambda_num > 65535) return TRS_EINVAL;
     bool ladder = p->dtile == -2 && p->drs == -2;
     if (!ladder && (p->dtile < -1 || p->drs < -1)) return TRS_EINVAL;
@@ -194,6 +195,30 @@ trs_status space_size(int W, int H, const trs_search_params *p, int64_t *n, int3
     *dt = a;
     *dr = b;
     return TRS_OK;
+}
+
+// The optional pruning rules (trs_search_params.prune) for candidate m of one (shape, Y, X):
+// bit 0, every tile's tallest slice is at most twice its shortest (pixel heights); bit 1,
+// every tile's mean slice area lies within [1/1.5, 1.5] times the mean slice area of the
+// other tiles.  Geometry only, like the area rule.
+static bool coherent_tiles(int prune, int N, int T, int M, int m, const uint16_t *cmb,
+                           const std::vector<int> &rowoff, const std::vector<int> &trow,
+                           const std::vector<int> &tcol, const std::vector<uint64_t> &wpx,
+                           const std::vector<uint64_t> &tile_hpx, const std::vector<uint64_t> &hmn,
+                           const std::vector<uint64_t> &hmx, const std::vector<int32_t> &optk,
+                           uint64_t frame_px)
+{
+    for (int t = 0; t < T; t++) {
+        const int ro = rowoff[trow[t]] + cmb[(size_t)t * M + m];
+        if ((prune & 1) && hmx[ro] > 2 * hmn[ro]) return false;
+        if (prune & 2) {
+            const int64_t k = optk[ro], rest = N - k;
+            if (rest <= 0) continue;
+            const int64_t a = (int64_t)(wpx[tcol[t]] * tile_hpx[trow[t]]), o = (int64_t)frame_px - a;
+            if (2 * a * rest > 3 * o * k || 3 * a * rest < 2 * o * k) return false;
+        }
+    }
+    return true;
 }
 
 trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
@@ -457,7 +482,9 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
                 cur_xa = -1;
                 cur_slices = 0;
             };
-            std::vector<uint64_t> wpx(c);
+            std::vector<uint64_t> wpx(c), tile_hpx(r);
+            for (int j = 0; j < r; j++) tile_hpx[j] = (uint64_t)(pl.rowpx[Y[j + 1]] - pl.rowpx[Y[j]]);
+            const uint64_t frame_px = (uint64_t)pl.colpx[W] * (uint64_t)pl.rowpx[H];
             std::vector<int> sidx(c), tcol(T), trow(T);
             for (int t = 0; t < T; t++) { tcol[t] = t % c; trow[t] = t / c; }
             for (int64_t xi = 0; xi < s.nX; xi++) {
@@ -472,6 +499,9 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
                         amax = std::max(amax, wpx[tcol[t]] * hmx[ro]);
                     }
                     if (p->area_k != 0 && !((uint64_t)p->area_k * amin > amax)) continue;
+                    if (p->prune && !coherent_tiles(p->prune, N, T, M, m, cmb, rowoff, trow, tcol, wpx,
+                                                    tile_hpx, hmn, hmx, optk, frame_px))
+                        continue;
                     if (!cur_f.empty() && ((int64_t)cur_desc.size() / 2 + T > kRecCap ||
                                            (int)cur_spans.size() + c > kSpanCap ||
                                            (xi - cur_xa + 1) * (int64_t)M > INT32_MAX)) {

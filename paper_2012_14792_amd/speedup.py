@@ -47,7 +47,7 @@ def sequence_speedup(frames_rects, frames_times, s: float = 0.0) -> float:
 
 
 def report(n_frames: int = 16, s: float = 0.04, sizes=("fhd", "uhd", "8k"), threads=(4, 8, 16),
-           device="cuda", keep_decisions: bool = False) -> dict:
+           device="cuda", keep_decisions: bool = False, prune: int = 0) -> dict:
     """For every (resolution, N) of the workloads: sigma of the uniform grid and of the chosen
     partitions, with and without the sequential share, and the Eq. 6 bound.  Partitions come
     from the batched GPU path on a seeded drifting sequence with the previous frame's realized
@@ -73,7 +73,7 @@ def report(n_frames: int = 16, s: float = 0.04, sizes=("fhd", "uhd", "8k"), thre
             lumas.append(luma)
         for N in threads:
             C, R, K = synth.BOUNDS[N]
-            params = B.make_params(N, C, R, K, lam=synth.LAMBDA[(name, N)])
+            params = B.make_params(N, C, R, K, lam=synth.LAMBDA[(name, N)], prune=prune)
             items = [dict(width=w, height=h, params=params, luma=lumas[f],
                           prev=torch.from_numpy(truth[f - 1].view(np.int32)).to(device))
                      for f in range(1, n_frames + 1)]
@@ -100,9 +100,14 @@ def report(n_frames: int = 16, s: float = 0.04, sizes=("fhd", "uhd", "8k"), thre
 
 
 def main():
+    import argparse
     import json
     import sys
-    res = report()
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--prune", type=int, default=0, help="pruning rules (bit 0 heights, bit 1 means)")
+    args = ap.parse_args()
+    res = report(n_frames=args.frames, prune=args.prune)
     print(f"{'workload':10s} {'lambda':>6s} {'uniform':>8s} {'proposed':>9s} {'unif(s)':>8s} "
           f"{'prop(s)':>8s} {'max(s)':>7s}", file=sys.stderr)
     for k, v in res.items():

@@ -267,3 +267,38 @@ def test_graph_replay_matches_eager(orc):
     for i, (f, luma, prev) in enumerate(frames):
         assert_same_result(B.read_result(graphed[i]), orc.partition(luma, prev, oracle_params(orc, p)),
                            f"graph frame {f}")
+
+
+@pytest.mark.parametrize("name,N,C,R,K,lam", [("fhd", 8, 6, 4, 4, (3, 10)), ("uhd", 8, 6, 4, 4, (1, 10)),
+                                               ("fhd", 4, 3, 3, 2, (0, 1))])
+@pytest.mark.parametrize("prune", [1, 2, 3])
+def test_search_with_pruning_rules_matches_oracle(orc, name, N, C, R, K, lam, prune):
+    """The optional pruning rules change the feasible set at plan time; per-frame searches and
+    a batch holding frames with different rule sets both give the oracle's results."""
+    import torch
+    w, h = synth.SIZES[name]
+    frame = B.make_frame(w, h)
+    gen = synth.SequenceGenerator(w, h, 40 + prune, 8.0)
+    luma = gen.frame(1)
+    f = orc.features(luma)
+    W, H = B.ctu_dims(frame)
+    prev = synth.ctu_times(orc.features(gen.frame(0))["tex"], synth.ar1_eps(W * H, 1, 5)[0])
+    cost, _ = orc.cost_map(f["tex"], prev)
+    params = B.make_params(N, C, R, K, lam=lam, prune=prune)
+    ref = orc.search(w, h, oracle_params(orc, params), cost, f["s1"], f["s2"])
+    gf = gpu_features(frame, to_device(luma))
+    got = gpu_search(frame, params, cost, gf["s1"], gf["s2"])
+    assert_same_result(got, ref, f"{name} prune {prune}")
+    # the same frame in a batch next to an unpruned copy
+    items = [dict(width=w, height=h, params=params, luma=to_device(luma),
+                  prev=torch.from_numpy(prev.view(np.int32)).cuda()),
+             dict(width=w, height=h, params=B.make_params(N, C, R, K, lam=lam), luma=to_device(luma),
+                  prev=torch.from_numpy(prev.view(np.int32)).cuda())]
+    batch = B.Batch(items)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    res = batch.results()
+    assert_same_result(res[0], ref, f"batch {name} prune {prune}")
+    ref0 = orc.search(w, h, oracle_params(orc, items[1]["params"]), cost, f["s1"], f["s2"])
+    assert_same_result(res[1], ref0, f"batch {name} unpruned")
+    batch.close()

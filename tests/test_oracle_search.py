@@ -240,3 +240,69 @@ def test_no_feasible_candidate_returns_uniform(orc):
     assert o["col_bd"] == [0, 7, 15] and o["row_bd"] == [0, 4, 9]
     assert o["rank"] == o["uniform_rank"] >= 0
     assert o["t_sel"] == o["t_unif"] == max(o["rs_time"])
+
+
+@pytest.mark.parametrize("w,h,N,seed", [(768, 600, 4, 1), (896, 640, 4, 7), (1024, 768, 5, 8)])
+@pytest.mark.parametrize("prune", [1, 2, 3])
+def test_pruning_rules_match_brute_force(orc, w, h, N, seed, prune):
+    """The optional pruning rules (the authors' commented notes): the oracle and the
+    independent brute force agree on the feasible set and the decision; each rule only
+    removes candidates and both together remove at least what each removes."""
+    luma, f, cost = _inputs(orc, w, h, seed)
+    counts = {}
+    for pr in (0, prune):
+        p = orc.make_params(N, 3, 3, 2, lam=(1, 10), prune=pr)
+        o = orc.search(w, h, p, cost, f["s1"], f["s2"])
+        b = brute.brute_search(luma, cost, 128, N, 3, 3, 2, lam=Fraction(1, 10), prune=pr)
+        assert o["n_enumerated"] == b["n_enumerated"] and o["n_feasible"] == b["n_feasible"]
+        counts[pr] = o["n_feasible"]
+        if b["rank"] is None:
+            assert o["status"] == 1
+            continue
+        assert (o["rank"], o["t_min"], o["t_sel"], o["q_sel"], o["rs"]) == \
+            (b["rank"], b["t_min"], b["t_sel"], b["q_sel"], b["rs"])
+    assert counts[prune] <= counts[0]
+    if prune == 3:
+        n1 = orc.search(w, h, orc.make_params(N, 3, 3, 2, prune=1), cost, f["s1"], f["s2"])["n_feasible"]
+        n2 = orc.search(w, h, orc.make_params(N, 3, 3, 2, prune=2), cost, f["s1"], f["s2"])["n_feasible"]
+        assert counts[3] <= min(n1, n2)
+
+
+def test_pruning_heights_by_hand():
+    """Bit 0 on a hand-checked geometry: 1 x 1 tile grid of a 128 x 640 frame (5 CTU rows),
+    4 slices: splits (1, 2, 3) give heights 128, 128, 128, 256 (kept: 256 = 2 x 128), splits
+    (1, 2, 4)... every candidate with a slice of 3 rows (384 > 2 x 128) next to a 1-row slice is
+    dropped."""
+    luma = np.full((640, 128), 100, np.uint16)
+    cost = [100] * 5
+    all4 = brute.enumerate_candidates(1, 5, 4, 1, 1, 4, None, None)
+    kept = []
+    for cand in all4:
+        rs = brute.regions_of(1, 5, cand)
+        if brute.coherent(cand, rs, lambda q: 128 * 128 * (q[3] - q[1]), [128] * 5, 4, 1):
+            kept.append(cand[4][0][1])
+    # 4 slices in 5 rows: one slice has 2 rows, the others 1 row: 256 <= 2 x 128, all kept
+    assert len(all4) == 4 and len(kept) == 4
+    all2 = brute.enumerate_candidates(1, 5, 2, 1, 1, 2, None, None)
+    kept2 = [c[4][0][1] for c in all2
+             if brute.coherent(c, brute.regions_of(1, 5, c), lambda q: 0, [128] * 5, 2, 1)]
+    # 2 slices: splits at 1 (1 + 4 rows) and 4 (4 + 1) break the rule, 2 and 3 (2 + 3) keep it
+    assert sorted(kept2) == [(2,), (3,)]
+    b = brute.brute_search(luma, cost, 128, 2, 1, 1, 2, lam=None, area_k=0, prune=1)
+    assert b["n_feasible"] == 2
+
+
+@pytest.mark.parametrize("wh,N,C,R,K", [((1920, 1080), 4, 3, 3, 2), ((1920, 1080), 8, 6, 4, 4),
+                                        ((3840, 2160), 8, 6, 4, 4)])
+@pytest.mark.parametrize("prune", [1, 2, 3])
+def test_plan_applies_pruning_like_the_oracle(orc, wh, N, C, R, K, prune):
+    """The library's plan (host only) keeps exactly the candidates the oracle keeps."""
+    from paper_2012_14792_amd import binding as B
+    w, h = wh
+    frame = B.make_frame(w, h)
+    st = B.trs_search_stats(frame, B.make_params(N, C, R, K, prune=prune))
+    W, H = orc.ctu_dims(w, h, 128)
+    flat = np.zeros(W * H, np.uint32)
+    o = orc.search(w, h, orc.make_params(N, C, R, K, prune=prune), flat + 1, flat, flat.astype(np.uint64))
+    assert st["feasible"] == o["n_feasible"]
+    assert st["candidates"] == o["n_enumerated"]
