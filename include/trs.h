@@ -289,6 +289,13 @@ trs_status trs_mlp_cost(const trs_frame *frame, const float *y, const float *x,
                         trs_blend blend, uint32_t *cost, uint32_t *n_fallback_dev,
                         hipStream_t stream);
 
+/* Host: the lambda of Eq. 4 that Table 1 pairs with the frame's resolution and thread count:
+ * frames up to 1080 lines take the FHD column, taller ones the UHD column; n_threads takes the
+ * nearest of the table's rows n = 4 (n <= 5), 8 (6 <= n <= 9) and 12 (n >= 10).  FHD: 0, 3/10,
+ * 1/10; UHD: 0, 1/10, 1/10.  Writes lambda = num / den.  Errors: TRS_EINVAL. */
+trs_status trs_lambda_policy(const trs_frame *frame, int32_t n_threads, int32_t *lambda_num,
+                             int32_t *lambda_den);
+
 /* Host: |C| and the windows (dtile, drs) the ladder rule picks.  No device work.
  * Errors: TRS_EINVAL. */
 trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params,

@@ -129,6 +129,9 @@ def lib():
         L.trs_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
         L.trs_profile_read.restype = S
+        L.trs_lambda_policy.argtypes = [ctypes.POINTER(Frame), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]
+        L.trs_lambda_policy.restype = S
         L.trs_profile_read_batch.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.trs_profile_read_batch.restype = S
         L.trs_batch_create.argtypes = [ctypes.POINTER(BatchFrame), ctypes.c_int32, ctypes.c_int32,
@@ -240,6 +243,14 @@ def trs_profile_read_batch() -> tuple[dict, int]:
     n = ctypes.c_int64()
     check(lib().trs_profile_read_batch(ms, ctypes.byref(n)), "trs_profile_read_batch")
     return dict(zip(BATCH_STAGES, list(ms))), n.value
+
+
+def trs_lambda_policy(frame: Frame, n_threads: int) -> tuple[int, int]:
+    """(num, den) of the lambda Table 1 pairs with the frame's resolution and thread count."""
+    num, den = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().trs_lambda_policy(ctypes.byref(frame), n_threads, ctypes.byref(num), ctypes.byref(den)),
+          "trs_lambda_policy")
+    return num.value, den.value
 
 
 def trs_release_plans() -> None:

@@ -286,6 +286,18 @@ trs_status trs_cost_map(const trs_frame *frame, const uint32_t *tex, const uint3
     return e == hipSuccess ? TRS_OK : TRS_EDEVICE;
 }
 
+trs_status trs_lambda_policy(const trs_frame *frame, int32_t n_threads, int32_t *lambda_num,
+                             int32_t *lambda_den)
+{
+    if (!frame_ok(frame) || n_threads < 1 || !lambda_num || !lambda_den) return TRS_EINVAL;
+    static const int32_t kNum[2][3] = {{0, 3, 1}, {0, 1, 1}};      // Table 1: [FHD, UHD][n = 4, 8, 12]
+    const int col = frame->height <= 1080 ? 0 : 1;
+    const int row = n_threads <= 5 ? 0 : n_threads <= 9 ? 1 : 2;
+    *lambda_num = kNum[col][row];
+    *lambda_den = 10;
+    return TRS_OK;
+}
+
 trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params, int64_t *n,
                           int32_t *dtile, int32_t *drs)
 {

@@ -160,3 +160,27 @@ def test_features_rejects_bad_layout(lib):
     assert L.trs_features(ctypes.byref(fr), ctypes.c_void_p(0x1000), 1920, bad, None) == B.TRS_EINVAL
     assert L.trs_cost_map(ctypes.byref(fr), ctypes.c_void_p(0x1000), None, B.Blend(200, 3, 257),
                           ctypes.c_void_p(0x2000), None, None) == B.TRS_EINVAL
+
+
+def test_lambda_policy_matches_table1():
+    """trs_lambda_policy returns the lambda Table 1 prints for each resolution and n, and maps
+    other thread counts and sizes to the nearest row and column."""
+    import json
+    from fractions import Fraction
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_lambda.json")))
+    for col, (w, h) in (("fhd", (1920, 1080)), ("uhd", (3840, 2160))):
+        for n, lam in g[col].items():
+            num, den = B.trs_lambda_policy(B.make_frame(w, h), int(n))
+            assert Fraction(num, den) == Fraction(*lam), (col, n)
+    assert B.trs_lambda_policy(B.make_frame(7680, 4320), 16) == B.trs_lambda_policy(B.make_frame(3840, 2160), 12)
+    assert B.trs_lambda_policy(B.make_frame(1280, 720), 6) == B.trs_lambda_policy(B.make_frame(1920, 1080), 8)
+    assert B.trs_lambda_policy(B.make_frame(1920, 1080), 2) == (0, 10)
+    with pytest.raises(B.TrsError):
+        B.trs_lambda_policy(B.make_frame(1920, 1080), 0)
+
+
+def test_workload_lambdas_follow_the_policy():
+    from fractions import Fraction
+    for (size, n), lam in synth.LAMBDA.items():
+        w, h = synth.SIZES[size]
+        assert Fraction(*B.trs_lambda_policy(B.make_frame(w, h), n)) == Fraction(*lam), (size, n)
