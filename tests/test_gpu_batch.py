@@ -246,3 +246,36 @@ def test_batch_split_calls_pipelined_over_streams(orc):
         assert torch.equal(torch.cat([h.out for h in halves]), whole.out)
     for bt in halves + [whole]:
         bt.close()
+
+
+def test_batch_wide_and_narrow_time_totals(orc):
+    """Frames whose predicted-time totals reach far beyond 2^32 (up to 2^31 - 1 per CTU) next to
+    ordinary ones, in chunks of each kind and a mixed chunk: the batch matches the oracle frame
+    by frame (record maxima and Eq. 4 bounds need the full 64 bits)."""
+    import torch
+    w, h = synth.SIZES["fhd"]
+    gen = synth.SequenceGenerator(w, h, 91, 8.0)
+    W, H = synth.ctu_grid(w, h)
+    frames = []
+    # chunks (8 frames each, in order): 0..7 all narrow, 8..15 narrow but for frame 12, 16..23 wide
+    for f in range(24):
+        luma = gen.frame(f)
+        prev = synth.ctu_times(orc.features(gen.frame(f + 1))["tex"], synth.ar1_eps(W * H, 1, 600 + f)[0])
+        if f >= 16:                                     # totals far above 2^32
+            prev = np.minimum(prev.astype(np.uint64) * (40000 + 997 * f), 2**31 - 1).astype(np.uint32)
+        if f == 12:
+            prev = np.full(W * H, 2**31 - 1, np.uint32)
+        frames.append(dict(width=w, height=h, luma_np=luma, prev_np=prev,
+                           params=B.make_params(8, 6, 4, 4, lam=(3, 10)), luma=to_device(luma),
+                           prev=torch.from_numpy(prev.view(np.int32)).cuda()))
+    assert int(frames[16]["prev_np"].astype(np.uint64).sum()) >= 2**32
+    assert int(frames[12]["prev_np"].astype(np.uint64).sum()) >= 2**32
+    assert all(int(frames[f]["prev_np"].astype(np.uint64).sum()) < 2**31 for f in range(8))
+    batch = B.Batch(frames)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    got = batch.results()
+    for i, fr in enumerate(frames):
+        ref = orc.partition(fr["luma_np"], fr["prev_np"], oracle_params(orc, fr["params"]))
+        assert_same_result(got[i], ref, f"frame {i}")
+    batch.close()
