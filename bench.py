@@ -199,6 +199,16 @@ def main():
     torch.cuda.synchronize()
     g_batch = capture(step_batch)
 
+    # single-frame latency: one trs_partition launch sequence on one stream (the paper's use,
+    # a frame partitioned just before it is encoded), graph-replayed back to back
+    one = B.Partitioner(w, h, params)
+    one_out = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    one.enqueue(luma[1], prev[1], out=one_out)
+    torch.cuda.synchronize()
+    g_one = capture(lambda: one.enqueue(luma[1], prev[1], out=one_out))
+    reps_one = max(200, 20 * args.steps)
+    _, el_one = time_graph(g_one, args.warmup, reps_one, 1)
+    latency_us = el_one / reps_one * 1e6
     fps_streams, el_streams = time_graph(g_streams, args.warmup, args.steps, F)
     outs_streams = outs.clone()
     fps_batch, el_batch = time_graph(g_batch, args.warmup, args.steps, F)
@@ -343,6 +353,7 @@ def main():
         "feasible_scored_per_s": round(fps * stats["feasible"], 1),
         "batched_value": round(fps_batch, 3),
         "per_frame_streams_value": round(fps_streams, 3),
+        "single_frame_latency_us": round(latency_us, 2),
         "eager_value": round(F * args.steps / eager_elapsed, 3),
         "kernel_ms": {k: round(v, 5) for k, v in kms.items()},
         "step2_fraction": round(step2_frac, 4),

@@ -302,3 +302,25 @@ def test_search_with_pruning_rules_matches_oracle(orc, name, N, C, R, K, lam, pr
     ref0 = orc.search(w, h, oracle_params(orc, items[1]["params"]), cost, f["s1"], f["s2"])
     assert_same_result(res[1], ref0, f"batch {name} unpruned")
     batch.close()
+
+
+@pytest.mark.parametrize("w,h,cs,N,C,R,K", [(8192, 8192, 128, 4, 3, 3, 2), (3840, 2160, 32, 4, 3, 3, 2),
+                                             (100, 100, 128, 1, 1, 1, 1), (1920, 1080, 128, 1, 1, 1, 1)])
+def test_full_path_extreme_sizes(orc, w, h, cs, N, C, R, K):
+    """The largest frame (8192 x 8192) and a 121 x 69 CTU grid (prefix sums beyond LDS, wave
+    scans), a single CTU and a single slice: the per-frame path equals the oracle's."""
+    import torch
+    luma = synth.make_frame(w, h, 21)
+    W, H = (w + cs - 1) // cs, (h + cs - 1) // cs
+    prev = synth.ctu_times(orc.features(luma, cs)["tex"], synth.ar1_eps(W * H, 1, 21)[0])
+    params = B.make_params(N, C, R, K, lam=(1, 10))
+    part = B.Partitioner(w, h, params, ctu_size=cs)
+    part.enqueue(to_device(luma), torch.from_numpy(prev.view(np.int32)).cuda())
+    got = B.read_result(part.out)
+    ref = orc.partition(luma, prev, oracle_params(orc, params), cs=cs)
+    assert_same_result(got, ref, f"{w}x{h} cs {cs} N {N}")
+    if (W + 1) * (H + 1) > 2304:                         # the batched form keeps grids in LDS
+        with pytest.raises(B.TrsError) as err:
+            B.Batch([dict(width=w, height=h, ctu_size=cs, params=params, luma=to_device(luma),
+                          prev=torch.from_numpy(prev.view(np.int32)).cuda())])
+        assert err.value.status == B.TRS_ENOTIMPL
