@@ -97,7 +97,14 @@ typedef struct trs_blend {
  *                   candidate with a tile whose largest slice height (pixels) exceeds twice its
  *                   smallest; bit 1 (TRS_PRUNE_MEANS) drops a candidate with a tile whose mean
  *                   slice area is above 1.5 times, or below 1/1.5 of, the mean area of the other
- *                   tiles' slices.  Like the area rule, they apply in both steps. */
+ *                   tiles' slices.  Like the area rule, they apply in both steps;
+ *   min_rs          smallest RS count of a candidate, 0..N; 0 (default) means N.  With
+ *                   min_rs < N the space holds partitions into n RS for every n in
+ *                   [min_rs, N], leaving N - n threads idle (Section 1 cites work in which
+ *                   fewer tiles than cores lower the coding loss); T~(P) is still the slowest
+ *                   RS (Eq. 1).  A shape (c, r) is valid when c r <= N and min_rs <= Kmax c r;
+ *                   the canonical order is unchanged, over tile choices whose k sum to any n
+ *                   in [min_rs, N]. */
 #define TRS_PRUNE_HEIGHTS 1
 #define TRS_PRUNE_MEANS 2
 typedef struct trs_search_params {
@@ -106,6 +113,7 @@ typedef struct trs_search_params {
     int32_t dtile, drs;
     int32_t sched_block, sched_item;
     int32_t prune;
+    int32_t min_rs;
     int64_t space_budget;
 } trs_search_params;
 

@@ -52,12 +52,14 @@ def boundary_vectors(L: int, m: int, d: int | None):
     return sorted(out)
 
 
-def enumerate_candidates(W, H, N, Cmax, Rmax, Kmax, dt, dr):
-    """Every candidate as a canonical key, sorted (the sort defines the rank)."""
+def enumerate_candidates(W, H, N, Cmax, Rmax, Kmax, dt, dr, n_lo=None):
+    """Every candidate as a canonical key, sorted (the sort defines the rank).  The RS count
+    of a candidate runs over [n_lo, N] (default: exactly N; fewer RS leave threads idle)."""
+    n_lo = N if n_lo is None else n_lo
     cands = []
     for c in range(1, Cmax + 1):
         for r in range(1, Rmax + 1):
-            if not (c * r <= N <= Kmax * c * r):
+            if not any(c * r <= n <= Kmax * c * r for n in range(n_lo, N + 1)):
                 continue
             Xs = boundary_vectors(W, c, dt)
             Ys = boundary_vectors(H, r, dt)
@@ -73,7 +75,7 @@ def enumerate_candidates(W, H, N, Cmax, Rmax, Kmax, dt, dr):
                                 opts.append((k, Z))
                         per_tile.extend([opts] * c)
                     for choice in itertools.product(*per_tile):
-                        if sum(k for k, _ in choice) == N:
+                        if n_lo <= sum(k for k, _ in choice) <= N:
                             cands.append((c, r, X, Y, choice))
     cands.sort(key=lambda t: (t[0], t[1], t[2], t[3], t[4]))
     return cands
@@ -93,7 +95,7 @@ def regions_of(W, H, cand):
     return rs
 
 
-def coherent(cand, rs, area, row_px, N, prune):
+def coherent(cand, rs, area, row_px, prune):
     """The authors' commented pruning notes as rules (pixel units): bit 0, the tallest slice of
     every tile is at most twice its shortest; bit 1, every tile's mean slice area is within
     [1/1.5, 1.5] times the mean slice area of the other tiles (when they hold any slice)."""
@@ -111,7 +113,7 @@ def coherent(cand, rs, area, row_px, N, prune):
         tile_area = [sum(area(q) for q in t) for t in tiles]
         total = sum(tile_area)
         for t, a in zip(tiles, tile_area):
-            k, rest = len(t), N - len(t)
+            k, rest = len(t), len(rs) - len(t)
             if rest <= 0:
                 continue
             mean_cur, mean_rem = Fraction(a, k), Fraction(total - a, rest)
@@ -121,7 +123,7 @@ def coherent(cand, rs, area, row_px, N, prune):
 
 
 def brute_search(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3,
-                 dt=None, dr=None, prune=0):
+                 dt=None, dr=None, prune=0, n_lo=None):
     """Returns dict(rank, t_min, t_sel, q_sel, rs, n_enumerated, n_feasible).
 
     `cost` is the per-CTU time map (raster, length W*H); lam is a Fraction or None (= inf).
@@ -131,7 +133,7 @@ def brute_search(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3,
     n, s1, s2, _ = ctu_stats_pixels(luma, cs)
     T = [[int(cost[y * W + x]) for x in range(W)] for y in range(H)]
     row_px = [min(cs, h - y * cs) for y in range(H)]
-    cands = enumerate_candidates(W, H, N, Cmax, Rmax, Kmax, dt, dr)
+    cands = enumerate_candidates(W, H, N, Cmax, Rmax, Kmax, dt, dr, n_lo)
 
     def rsum(a, rect):
         x0, y0, x1, y1 = rect
@@ -142,7 +144,7 @@ def brute_search(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3,
         rs = regions_of(W, H, cand)
         areas = [rsum(n, q) for q in rs]
         feasible = (area_k == 0 or area_k * min(areas) > max(areas)) and \
-            coherent(cand, rs, lambda q: rsum(n, q), row_px, N, prune)
+            coherent(cand, rs, lambda q: rsum(n, q), row_px, prune)
         t = max(rsum(T, q) for q in rs)
         qv = sum(rsum(s2, q) - (rsum(s1, q) ** 2) // rsum(n, q) for q in rs)
         scored.append((rank, feasible, t, qv, rs))

@@ -57,6 +57,7 @@ typedef struct {
     int32_t n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile, area_k;
     int32_t lambda_num, lambda_den, dtile, drs;
     int32_t prune;          /* bit 0: slice heights within 2x in a tile; bit 1: tile mean areas */
+    int32_t min_rs;         /* RS counts n in [min_rs, N] (idle threads); 0 means N */
     int64_t space_budget;
 } orc_params;
 
@@ -222,11 +223,18 @@ static vec_list gen_vectors(int m, int L, int d)
     return out;
 }
 
-/* |C| for a window pair: sum over shapes of |X| * sum over Y of [z^N] prod_j P_{h_j}(z)^c,
- * where P_h(z) = sum_k z^k * (number of split vectors of a height-h tile into k slices). */
+/* Smallest RS count of a candidate: min_rs, or N when it is 0. */
+static int rs_lo(const orc_params *p)
+{
+    return p->min_rs > 0 ? p->min_rs : p->n_threads;
+}
+
+/* |C| for a window pair: sum over shapes of |X| * sum over Y of the coefficients of z^n,
+ * n = min_rs .. N, of prod_j P_{h_j}(z)^c, where P_h(z) = sum_k z^k * (number of split
+ * vectors of a height-h tile into k slices). */
 static uint64_t space_size(int W, int H, const orc_params *p, int dt, int dr)
 {
-    int N = p->n_threads, Km = p->max_rs_per_tile;
+    int N = p->n_threads, Km = p->max_rs_per_tile, Nlo = rs_lo(p);
     uint64_t total = 0;
     uint64_t splits[257][ORC_MAXN + 1];
     for (int h = 1; h <= H; h++)
@@ -234,7 +242,7 @@ static uint64_t space_size(int W, int H, const orc_params *p, int dt, int dr)
             splits[h][k] = (k >= 1 && k <= Km && k <= h) ? count_vectors(k, h, dr) : 0;
     for (int c = 1; c <= p->max_tile_cols; c++) {
         for (int r = 1; r <= p->max_tile_rows; r++) {
-            if (!((int64_t)c * r <= N && (int64_t)N <= (int64_t)Km * c * r)) continue;
+            if (!((int64_t)c * r <= N && (int64_t)Nlo <= (int64_t)Km * c * r)) continue;
             uint64_t nx = count_vectors(c, W, dt);
             if (nx == 0) continue;
             vec_list ys = gen_vectors(r, H, dt);
@@ -256,7 +264,7 @@ static uint64_t space_size(int W, int H, const orc_params *p, int dt, int dr)
                         memcpy(poly, q, sizeof(q));
                     }
                 }
-                sum_m = sat_add(sum_m, poly[N]);
+                for (int n = Nlo; n <= N; n++) sum_m = sat_add(sum_m, poly[n]);
             }
             free(ys.v);
             total = sat_add(total, sat_mul(nx, sum_m));
@@ -295,7 +303,7 @@ int orc_space_size(int W, int H, const orc_params *p, int64_t *n, int32_t *dt, i
 
 typedef struct {
     /* geometry */
-    int W, H, N, Km, karea, cs, prune;
+    int W, H, N, Nlo, Km, karea, cs, prune;
     int64_t *colpx, *rowpx;                /* pixel prefix: colpx[x] = width of CTU cols < x */
     int64_t *satT, *satS1, *satS2;         /* (H+1) x (W+1) inclusive prefix sums */
     int64_t lam_num, lam_den;
@@ -353,12 +361,14 @@ static int is_uniform(const search_ctx *s)
  * candidate (pixel units, as the area rule):
  *   heights: in every tile, the tallest slice is at most twice the shortest;
  *   means:   in every tile, mean slice area = tile area / k lies within [1/1.5, 1.5] times the
- *            mean slice area over the other tiles (other area / (N - k)), when N > k.
+ *            mean slice area over the other tiles (other area / (n - k), n the candidate's RS
+ *            count), when n > k.
  * Returns 1 when the candidate passes the rules selected by s->prune. */
 static int coherent(const search_ctx *s)
 {
     if (!s->prune) return 1;
-    int64_t total = 0, tarea[ORC_MAXN];
+    int64_t total = 0, tarea[ORC_MAXN], n = 0;
+    for (int t = 0; t < s->c * s->r; t++) n += s->k[t];
     for (int j = 0; j < s->r; j++)
         for (int i = 0; i < s->c; i++) {
             const int t = j * s->c + i;
@@ -375,7 +385,7 @@ static int coherent(const search_ctx *s)
         }
     if (s->prune & 2)
         for (int t = 0; t < s->c * s->r; t++) {
-            const int64_t k = s->k[t], rest = s->N - k;
+            const int64_t k = s->k[t], rest = n - k;
             if (rest <= 0) continue;
             const int64_t a = tarea[t], o = total - tarea[t];
             /* a / k > 1.5 o / rest  or  a / k < o / (1.5 rest) */
@@ -460,14 +470,14 @@ static void enum_tiles(search_ctx *s, int t, int remaining)
 {
     int T = s->c * s->r;
     if (t == T) {
-        if (remaining == 0) evaluate(s);
+        if (remaining <= s->N - s->Nlo) evaluate(s);     /* remaining threads stay idle */
         return;
     }
     int h = s->Y[t / s->c + 1] - s->Y[t / s->c];
     int later = T - t - 1;                    /* tiles after this one, each needs 1..Km */
     for (int k = 1; k <= s->Km && k <= h && k <= remaining; k++) {
         if (remaining - k < later) break;     /* no slice left for some later tile */
-        if (remaining - k > later * s->Km) continue;  /* later tiles cannot absorb the rest */
+        if (remaining - k - later * s->Km > s->N - s->Nlo) continue;  /* too many idle threads */
         s->k[t] = k;
         s->Z[t][0] = 0;
         enum_splits(s, t, 1, remaining);
@@ -479,7 +489,7 @@ static void run_pass(search_ctx *s, int dt, const orc_params *p)
     s->rank = 0;
     for (int c = 1; c <= p->max_tile_cols; c++) {
         for (int r = 1; r <= p->max_tile_rows; r++) {
-            if (!((int64_t)c * r <= s->N && (int64_t)s->N <= (int64_t)s->Km * c * r)) continue;
+            if (!((int64_t)c * r <= s->N && (int64_t)s->Nlo <= (int64_t)s->Km * c * r)) continue;
             vec_list xs = gen_vectors(c, s->W, dt);
             vec_list ys = gen_vectors(r, s->H, dt);
             s->c = c;
@@ -539,7 +549,8 @@ int orc_search(int w, int h, int cs, const orc_params *p, const uint32_t *cost,
     if (w <= 0 || h <= 0 || cs <= 0) return -1;
     int W = (w + cs - 1) / cs, H = (h + cs - 1) / cs;
     if (p->n_threads < 1 || p->n_threads > ORC_MAXN || p->max_tile_cols < 1 || p->max_tile_rows < 1 ||
-        p->max_rs_per_tile < 1 || p->lambda_den < 1 || p->area_k < 0 || p->prune < 0 || p->prune > 3)
+        p->max_rs_per_tile < 1 || p->lambda_den < 1 || p->area_k < 0 || p->prune < 0 || p->prune > 3 ||
+        p->min_rs < 0 || p->min_rs > p->n_threads)
         return -1;
     int64_t n_space; int32_t dt, dr;
     if (orc_space_size(W, H, p, &n_space, &dt, &dr) != 0) return -1;
@@ -547,7 +558,8 @@ int orc_search(int w, int h, int cs, const orc_params *p, const uint32_t *cost,
 
     search_ctx s;
     memset(&s, 0, sizeof(s));
-    s.W = W; s.H = H; s.N = p->n_threads; s.Km = p->max_rs_per_tile; s.karea = p->area_k; s.cs = cs;
+    s.W = W; s.H = H; s.N = p->n_threads; s.Nlo = rs_lo(p); s.Km = p->max_rs_per_tile;
+    s.karea = p->area_k; s.cs = cs;
     s.prune = p->prune;
     s.dr = dr;
     s.lam_num = p->lambda_num; s.lam_den = p->lambda_den;

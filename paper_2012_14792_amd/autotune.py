@@ -42,7 +42,8 @@ def arch() -> str:
 def frame_key(width, height, params) -> str:
     p = params
     return (f"{arch()}|{width}x{height}|N{p.n_threads}|C{p.max_tile_cols}R{p.max_tile_rows}"
-            f"K{p.max_rs_per_tile}|k{p.area_k}|w{p.dtile},{p.drs}" + (f"|p{p.prune}" if p.prune else ""))
+            f"K{p.max_rs_per_tile}|k{p.area_k}|w{p.dtile},{p.drs}" + (f"|p{p.prune}" if p.prune else "")
+            + (f"|n{p.min_rs}" if p.min_rs else ""))
 
 
 def load_all() -> dict:

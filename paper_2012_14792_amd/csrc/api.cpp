@@ -25,7 +25,7 @@ struct PlanEntry {
     std::map<int, std::pair<void *, trs::SpaceView>> dev;   // per device: blob and view
 };
 
-using PlanKey = std::array<int64_t, 13>;
+using PlanKey = std::array<int64_t, 14>;
 
 std::mutex g_mu;
 std::map<PlanKey, PlanEntry> g_plans;
@@ -53,7 +53,8 @@ PlanKey plan_key(const trs_frame *f, const trs_search_params *p)
 {
     return {f->width, f->height, f->ctu_size, p->n_threads, p->max_tile_cols, p->max_tile_rows,
             p->max_rs_per_tile, p->dtile, p->drs, p->area_k,
-            p->space_budget > 0 ? p->space_budget : (int64_t(1) << 24), p->sched_item, p->prune};
+            p->space_budget > 0 ? p->space_budget : (int64_t(1) << 24), p->sched_item, p->prune,
+            p->min_rs > 0 ? p->min_rs : p->n_threads};
 }
 
 // Host tables for (f, p), built once.  Caller holds g_mu.

@@ -105,10 +105,16 @@ void poly_mul(const std::vector<u64> &a, const std::vector<u64> &b, std::vector<
     }
 }
 
+// Smallest RS count of a candidate (trs_search_params.min_rs; 0 means N).
+int rs_floor(const trs_search_params *p)
+{
+    return p->min_rs > 0 ? p->min_rs : p->n_threads;
+}
+
 // |C| for one window pair, by a DP over tile-row boundaries (no enumeration of Y).
 u64 space_count(int W, int H, const trs_search_params *p, int dt, int dr)
 {
-    const int N = p->n_threads, Km = p->max_rs_per_tile;
+    const int N = p->n_threads, Km = p->max_rs_per_tile, Nlo = rs_floor(p);
     std::vector<std::vector<u64>> P(H + 1);
     for (int h = 1; h <= H; h++) tile_poly(h, N, Km, dr, P[h]);
     u64 total = 0;
@@ -124,7 +130,7 @@ u64 space_count(int W, int H, const trs_search_params *p, int dt, int dr)
             Pc[h] = acc;
         }
         for (int r = 1; r <= p->max_tile_rows; r++) {
-            if (!((int64_t)c * r <= N && (int64_t)N <= (int64_t)Km * c * r)) continue;
+            if (!((int64_t)c * r <= N && (int64_t)Nlo <= (int64_t)Km * c * r)) continue;
             if (r > H) continue;
             // F[y] = polynomial over ways to place the first j row boundaries ending at y
             std::vector<std::vector<u64>> F(H + 1, std::vector<u64>(N + 1, 0)), G;
@@ -145,7 +151,7 @@ u64 space_count(int W, int H, const trs_search_params *p, int dt, int dr)
                 }
                 F.swap(G);
             }
-            total = sadd(total, smul(nx, F[H][N]));
+            for (int q = Nlo; q <= N; q++) total = sadd(total, smul(nx, F[H][q]));
         }
     }
     return total;
@@ -166,6 +172,7 @@ trs_status check_space_args(const trs_frame *f, const trs_search_params *p)
     if (p->max_tile_cols > kMaxRS || p->max_tile_rows > kMaxRS) return TRS_EINVAL;
     if (p->area_k < 0 || p->area_k > 1000000) return TRS_EINVAL;
     if (p->prune < 0 || p->prune > 3) return TRS_EINVAL;
+    if (p->min_rs < 0 || p->min_rs > p->n_threads) return TRS_EINVAL;
     if (p->lambda_den < 1 || p->lambda_den > 65535 || p->lambda_num > 65535) return TRS_EINVAL;
     bool ladder = p->dtile == -2 && p->drs == -2;
     if (!ladder && (p->dtile < -1 || p->drs < -1)) return TRS_EINVAL;
@@ -201,18 +208,20 @@ trs_status space_size(int W, int H, const trs_search_params *p, int64_t *n, int3
 // bit 0, every tile's tallest slice is at most twice its shortest (pixel heights); bit 1,
 // every tile's mean slice area lies within [1/1.5, 1.5] times the mean slice area of the
 // other tiles.  Geometry only, like the area rule.
-static bool coherent_tiles(int prune, int N, int T, int M, int m, const uint16_t *cmb,
+static bool coherent_tiles(int prune, int T, int M, int m, const uint16_t *cmb,
                            const std::vector<int> &rowoff, const std::vector<int> &trow,
                            const std::vector<int> &tcol, const std::vector<uint64_t> &wpx,
                            const std::vector<uint64_t> &tile_hpx, const std::vector<uint64_t> &hmn,
                            const std::vector<uint64_t> &hmx, const std::vector<int32_t> &optk,
                            uint64_t frame_px)
 {
+    int64_t n = 0;
+    for (int t = 0; t < T; t++) n += optk[rowoff[trow[t]] + cmb[(size_t)t * M + m]];
     for (int t = 0; t < T; t++) {
         const int ro = rowoff[trow[t]] + cmb[(size_t)t * M + m];
         if ((prune & 1) && hmx[ro] > 2 * hmn[ro]) return false;
         if (prune & 2) {
-            const int64_t k = optk[ro], rest = N - k;
+            const int64_t k = optk[ro], rest = n - k;
             if (rest <= 0) continue;
             const int64_t a = (int64_t)(wpx[tcol[t]] * tile_hpx[trow[t]]), o = (int64_t)frame_px - a;
             if (2 * a * rest > 3 * o * k || 3 * a * rest < 2 * o * k) return false;
@@ -227,7 +236,7 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
     if (st != TRS_OK) return st;
     const int cs = f->ctu_size;
     const int W = (f->width + cs - 1) / cs, H = (f->height + cs - 1) / cs;
-    const int N = p->n_threads, Km = p->max_rs_per_tile;
+    const int N = p->n_threads, Km = p->max_rs_per_tile, Nlo = rs_floor(p);
     pl.width = f->width;
     pl.height = f->height;
     pl.cs = cs;
@@ -258,7 +267,7 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
     const int64_t vec_cap = int64_t(1) << 24;
     for (int c = 1; c <= p->max_tile_cols; c++) {
         for (int r = 1; r <= p->max_tile_rows; r++) {
-            if (!((int64_t)c * r <= N && (int64_t)N <= (int64_t)Km * c * r)) continue;
+            if (!((int64_t)c * r <= N && (int64_t)Nlo <= (int64_t)Km * c * r)) continue;
             ShapeHost s{c, r, {}, {}, 0, 0};
             if (!list_vectors(c, W, dt, vec_cap, s.X, s.nX)) return TRS_ENOSPACE;
             if (!list_vectors(r, H, dt, vec_cap, s.Y, s.nY)) return TRS_ENOSPACE;
@@ -316,9 +325,10 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
         for (int64_t yi = 0; yi < s.nY; yi++) {
             const uint16_t *Y = &s.Y[yi * (r + 1)];
             for (int t = 0; t < T; t++) heights[t] = Y[t / c + 1] - Y[t / c];
-            // comp[t][n]: ways for tiles t..T-1 to hold n slices (saturating)
+            // comp[t][n]: ways for tiles t..T-1 to take slices from n free threads, leaving
+            // at most N - Nlo of them idle (saturating)
             std::vector<u64> comp((size_t)(T + 1) * (N + 1), 0);
-            comp[(size_t)T * (N + 1) + 0] = 1;
+            for (int n = 0; n <= N - Nlo; n++) comp[(size_t)T * (N + 1) + n] = 1;
             for (int t = T - 1; t >= 0; t--) {
                 int h = heights[t];
                 for (int n = 0; n <= N; n++) {
@@ -499,7 +509,7 @@ trs_status build_plan(const trs_frame *f, const trs_search_params *p, Plan &pl)
                         amax = std::max(amax, wpx[tcol[t]] * hmx[ro]);
                     }
                     if (p->area_k != 0 && !((uint64_t)p->area_k * amin > amax)) continue;
-                    if (p->prune && !coherent_tiles(p->prune, N, T, M, m, cmb, rowoff, trow, tcol, wpx,
+                    if (p->prune && !coherent_tiles(p->prune, T, M, m, cmb, rowoff, trow, tcol, wpx,
                                                     tile_hpx, hmn, hmx, optk, frame_px))
                         continue;
                     if (!cur_f.empty() && ((int64_t)cur_desc.size() / 2 + T > kRecCap ||

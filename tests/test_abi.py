@@ -51,6 +51,30 @@ def test_space_size_matches_oracle(lib, orc, w, h, N, C, R, K):
     assert B.trs_space_size(fr, pr) == orc.space_size(W, H, orc.make_params(N, C, R, K))
 
 
+@pytest.mark.parametrize("w,h,N,C,R,K,lo", [(1920, 1080, 8, 6, 4, 4, 4), (3840, 2160, 8, 6, 4, 4, 6),
+                                            (3840, 2160, 12, 6, 4, 4, 9), (7680, 4320, 16, 8, 6, 4, 1),
+                                            (384, 256, 8, 3, 2, 2, 1)])
+def test_space_size_with_idle_threads_matches_oracle(lib, orc, w, h, N, C, R, K, lo):
+    fr, pr = B.make_frame(w, h), B.make_params(N, C, R, K, min_rs=lo)
+    W, H = B.ctu_dims(fr)
+    assert B.trs_space_size(fr, pr) == orc.space_size(W, H, orc.make_params(N, C, R, K, min_rs=lo))
+
+
+@pytest.mark.parametrize("w,h,N,C,R,K,lo", [(768, 600, 4, 3, 3, 2, 1), (640, 512, 5, 3, 3, 2, 2),
+                                            (384, 256, 8, 3, 2, 2, 1)])
+def test_decode_with_idle_threads_follows_canonical_order(lib, w, h, N, C, R, K, lo):
+    """With RS counts in [min_rs, N], every rank still decodes to the candidate the brute
+    force puts at that position."""
+    fr, pr = B.make_frame(w, h), B.make_params(N, C, R, K, dtile=-1, drs=-1, min_rs=lo)
+    W, H = B.ctu_dims(fr)
+    cands = brute.enumerate_candidates(W, H, N, C, R, K, None, None, lo)
+    assert B.trs_space_size(fr, pr)[0] == len(cands)
+    for rank, cand in enumerate(cands):
+        d = B.trs_decode(fr, pr, rank)
+        assert d["rs"] == brute.regions_of(W, H, cand), rank
+        assert d["n_rs"] == len(d["rs"]) >= lo
+
+
 @pytest.mark.parametrize("w,h,N,C,R,K,dt,dr", [(640, 512, 3, 3, 3, 2, -1, -1),
                                                (768, 600, 4, 3, 3, 2, -1, -1),
                                                (1024, 768, 4, 3, 3, 2, 1, 0),
@@ -107,7 +131,8 @@ def test_invalid_frame(lib, frame):
 @pytest.mark.parametrize("kw", [dict(n_threads=0), dict(n_threads=65), dict(max_tile_cols=0),
                                 dict(max_rs_per_tile=0), dict(area_k=-1), dict(lam=(1, 0)),
                                 dict(lam=(70000, 1)), dict(dtile=-3, drs=0), dict(dtile=-2, drs=1),
-                                dict(sched_block=96), dict(sched_item=-5)])
+                                dict(sched_block=96), dict(sched_item=-5), dict(min_rs=-1),
+                                dict(min_rs=5), dict(prune=4)])
 def test_invalid_params(lib, kw):
     base = dict(n_threads=4, max_tile_cols=3, max_tile_rows=3, max_rs_per_tile=2)
     base.update(kw)

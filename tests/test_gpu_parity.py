@@ -304,6 +304,47 @@ def test_search_with_pruning_rules_matches_oracle(orc, name, N, C, R, K, lam, pr
     batch.close()
 
 
+@pytest.mark.parametrize("name,N,C,R,K,lam,lo,prune", [("fhd", 4, 3, 3, 2, (0, 1), 1, 0),
+                                                        ("fhd", 8, 6, 4, 4, (3, 10), 4, 2),
+                                                        ("uhd", 8, 6, 4, 4, (1, 10), 6, 0),
+                                                        ("uhd", 12, 6, 4, 4, (-1, 1), 9, 3),
+                                                        ("small", 8, 3, 2, 2, (1, 10), 1, 0)])
+def test_search_with_idle_threads_matches_oracle(orc, name, N, C, R, K, lam, lo, prune):
+    """RS counts in [min_rs, N] (idle threads): the plan holds every RS count of the range;
+    per-frame searches and a batch mixing it with the exact-N space equal the oracle.  The
+    3 x 2 CTU frame has no partition into 8 RS, only into fewer."""
+    import torch
+    w, h = synth.SIZES[name] if name != "small" else (384, 256)
+    frame = B.make_frame(w, h)
+    gen = synth.SequenceGenerator(w, h, 60 + lo, 8.0)
+    luma = gen.frame(1)
+    f = orc.features(luma)
+    W, H = B.ctu_dims(frame)
+    prev = synth.ctu_times(orc.features(gen.frame(0))["tex"], synth.ar1_eps(W * H, 1, 7)[0])
+    cost, _ = orc.cost_map(f["tex"], prev)
+    params = B.make_params(N, C, R, K, lam=lam, prune=prune, min_rs=lo)
+    ref = orc.search(w, h, oracle_params(orc, params), cost, f["s1"], f["s2"])
+    assert lo <= ref["n_rs"] <= N
+    gf = gpu_features(frame, to_device(luma))
+    got = gpu_search(frame, params, cost, gf["s1"], gf["s2"])
+    assert_same_result(got, ref, f"{name} N {N} min_rs {lo}")
+    exact = B.make_params(N, C, R, K, lam=lam, prune=prune)
+    if B.trs_space_size(frame, exact)[0] == 0:
+        with pytest.raises(B.TrsError):
+            gpu_search(frame, exact, cost, gf["s1"], gf["s2"])
+        exact = params
+    items = [dict(width=w, height=h, params=p, luma=to_device(luma),
+                  prev=torch.from_numpy(prev.view(np.int32)).cuda()) for p in (params, exact)]
+    batch = B.Batch(items)
+    batch.enqueue()
+    torch.cuda.synchronize()
+    res = batch.results()
+    batch.close()
+    assert_same_result(res[0], ref, f"batch {name} min_rs {lo}")
+    ref_exact = orc.search(w, h, oracle_params(orc, exact), cost, f["s1"], f["s2"])
+    assert_same_result(res[1], ref_exact, f"batch {name} exact N")
+
+
 @pytest.mark.parametrize("w,h,cs,N,C,R,K", [(8192, 8192, 128, 4, 3, 3, 2), (3840, 2160, 32, 4, 3, 3, 2),
                                              (100, 100, 128, 1, 1, 1, 1), (1920, 1080, 128, 1, 1, 1, 1)])
 def test_full_path_extreme_sizes(orc, w, h, cs, N, C, R, K):

@@ -279,13 +279,13 @@ def test_pruning_heights_by_hand():
     kept = []
     for cand in all4:
         rs = brute.regions_of(1, 5, cand)
-        if brute.coherent(cand, rs, lambda q: 128 * 128 * (q[3] - q[1]), [128] * 5, 4, 1):
+        if brute.coherent(cand, rs, lambda q: 128 * 128 * (q[3] - q[1]), [128] * 5, 1):
             kept.append(cand[4][0][1])
     # 4 slices in 5 rows: one slice has 2 rows, the others 1 row: 256 <= 2 x 128, all kept
     assert len(all4) == 4 and len(kept) == 4
     all2 = brute.enumerate_candidates(1, 5, 2, 1, 1, 2, None, None)
     kept2 = [c[4][0][1] for c in all2
-             if brute.coherent(c, brute.regions_of(1, 5, c), lambda q: 0, [128] * 5, 2, 1)]
+             if brute.coherent(c, brute.regions_of(1, 5, c), lambda q: 0, [128] * 5, 1)]
     # 2 slices: splits at 1 (1 + 4 rows) and 4 (4 + 1) break the rule, 2 and 3 (2 + 3) keep it
     assert sorted(kept2) == [(2,), (3,)]
     b = brute.brute_search(luma, cost, 128, 2, 1, 1, 2, lam=None, area_k=0, prune=1)
@@ -306,3 +306,71 @@ def test_plan_applies_pruning_like_the_oracle(orc, wh, N, C, R, K, prune):
     o = orc.search(w, h, orc.make_params(N, C, R, K, prune=prune), flat + 1, flat, flat.astype(np.uint64))
     assert st["feasible"] == o["n_feasible"]
     assert st["candidates"] == o["n_enumerated"]
+
+
+@pytest.mark.parametrize("w,h,N,lo,seed,prune", [(768, 600, 4, 1, 1, 0), (640, 512, 4, 2, 0, 0),
+                                                 (896, 384, 5, 3, 4, 0), (768, 600, 4, 1, 2, 3),
+                                                 (1024, 768, 5, 1, 8, 2)])
+@pytest.mark.parametrize("lam", [(0, 1), (3, 10), (-1, 1)])
+def test_idle_threads_match_brute_force(orc, w, h, N, lo, seed, prune, lam):
+    """RS counts in [min_rs, N] (N - n threads idle): the oracle and the independent brute
+    force (candidates filtered on their own RS count) agree on the space, the feasible set
+    and the decision, with and without the pruning rules (bit 1 compares against the other
+    tiles of the candidate's own RS count)."""
+    luma, f, cost = _inputs(orc, w, h, seed)
+    p = orc.make_params(N, 3, 3, 2, lam=lam, prune=prune, min_rs=lo)
+    o = orc.search(w, h, p, cost, f["s1"], f["s2"])
+    b = brute.brute_search(luma, cost, 128, N, 3, 3, 2, lam=_frac(lam), prune=prune, n_lo=lo)
+    assert o["n_enumerated"] == b["n_enumerated"]
+    assert o["n_feasible"] == b["n_feasible"]
+    if b["rank"] is None:
+        assert o["status"] == 1
+        return
+    assert (o["rank"], o["t_min"], o["t_sel"], o["q_sel"], o["rs"]) == \
+        (b["rank"], b["t_min"], b["t_sel"], b["q_sel"], b["rs"])
+    assert o["n_rs"] == len(o["rs"]) and lo <= o["n_rs"] <= N
+
+
+@pytest.mark.parametrize("W,H,N,C,R,K,dt,dr", [(15, 9, 4, 3, 3, 2, -1, -1), (30, 17, 8, 6, 4, 4, 3, 1),
+                                               (60, 34, 16, 8, 6, 4, 1, 0), (8, 8, 6, 3, 3, 3, -1, -1)])
+def test_idle_thread_space_is_union_of_exact_spaces(orc, W, H, N, C, R, K, dt, dr):
+    """At fixed windows, the space with RS counts in [lo, N] is the disjoint union of the
+    exact-count spaces for n = lo .. N (a candidate with n RS has c r <= n <= Kmax c r), so
+    the sizes add up; the exact-count sizes come from separate runs with N = n."""
+    for lo in sorted({1, max(1, N // 2), N}):
+        n_union = orc.space_size(W, H, orc.make_params(N, C, R, K, dtile=dt, drs=dr, min_rs=lo))[0]
+        parts = sum(orc.space_size(W, H, orc.make_params(n, C, R, K, dtile=dt, drs=dr))[0]
+                    for n in range(lo, N + 1))
+        assert n_union == parts
+
+
+def test_idle_threads_widen_step_one(orc):
+    """More candidates can only lower the step-1 minimum: T~min over [lo, N] RS is the
+    minimum of the exact-count minima, and the partition chosen with lambda = inf has the
+    smallest Q over the union."""
+    w, h, N = 1024, 768, 5
+    luma, f, cost = _inputs(orc, w, h, 8)
+    per_n = [orc.search(w, h, orc.make_params(n, 3, 3, 2, dtile=-1, drs=-1, lam=(-1, 1)),
+                        cost, f["s1"], f["s2"]) for n in range(2, N + 1)]
+    u = orc.search(w, h, orc.make_params(N, 3, 3, 2, dtile=-1, drs=-1, lam=(-1, 1), min_rs=2),
+                   cost, f["s1"], f["s2"])
+    feas = [r for r in per_n if r["status"] == 0]
+    assert u["t_min"] == min(r["t_min"] for r in feas)
+    assert u["q_sel"] == min(r["q_sel"] for r in feas)
+    assert u["n_feasible"] == sum(r["n_feasible"] for r in per_n)
+
+
+def test_idle_threads_on_a_frame_smaller_than_n(orc):
+    """A 3 x 2 CTU frame cannot hold 8 RS: the exact space is empty, while with min_rs <= 6
+    the space holds partitions into 1..6 RS, and the oracle equals the brute force."""
+    w, h = 384, 256
+    luma, f, cost = _inputs(orc, w, h, 3)
+    assert orc.space_size(3, 2, orc.make_params(8, 3, 2, 2, dtile=-1, drs=-1))[0] == 0
+    for lo, size in ((1, 22), (4, 12), (6, 2)):
+        p = orc.make_params(8, 3, 2, 2, lam=(1, 10), dtile=-1, drs=-1, min_rs=lo)
+        assert orc.space_size(3, 2, p)[0] == size
+        o = orc.search(w, h, p, cost, f["s1"], f["s2"])
+        b = brute.brute_search(luma, cost, 128, 8, 3, 2, 2, lam=Fraction(1, 10), n_lo=lo)
+        assert o["n_enumerated"] == b["n_enumerated"] == size
+        assert (o["rank"], o["t_min"], o["q_sel"], o["rs"]) == (b["rank"], b["t_min"], b["q_sel"], b["rs"])
+        assert o["n_rs"] == 6
