@@ -304,6 +304,20 @@ trs_status trs_mlp_cost(const trs_frame *frame, const float *y, const float *x,
 trs_status trs_lambda_policy(const trs_frame *frame, int32_t n_threads, int32_t *lambda_num,
                              int32_t *lambda_den);
 
+/* Host: which earlier frame's CTU times predict each frame of a random-access sequence
+ * (Section 2.1: in RA coding the co-located CTU of the previously coded frame of the same
+ * temporal layer, the co-TL frame, predicts better than the closest frame in time).
+ * gop_size G: a power of two, 1..256; frames 0 .. n_frames - 1 in display order, n_frames in
+ * 1 .. 2^24.  Dyadic hierarchy: frame p is in temporal layer 0 when G divides p, else
+ * log2(G) - (trailing zero bits of p).  Coding order: frame 0, then per GOP its last frame and,
+ * depth first, the midpoint of each open interval before its left and then its right half;
+ * frames past the end are skipped.  Outputs (host arrays of n_frames entries, caller-owned):
+ * coding_order[i] = frame coded i-th; layer[p]; cotl_ref[p] = the frame of layer[p] coded
+ * last before p, or -1; closest_ref[p] = the frame coded before p nearest to it in display
+ * order (ties: the earlier one), or -1 for frame 0.  Errors: TRS_EINVAL. */
+trs_status trs_ra_schedule(int32_t gop_size, int32_t n_frames, int32_t *coding_order,
+                           int32_t *layer, int32_t *cotl_ref, int32_t *closest_ref);
+
 /* Host: |C| and the windows (dtile, drs) the ladder rule picks.  No device work.
  * Errors: TRS_EINVAL. */
 trs_status trs_space_size(const trs_frame *frame, const trs_search_params *params,

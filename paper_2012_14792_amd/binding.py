@@ -133,6 +133,9 @@ def lib():
         L.trs_lambda_policy.argtypes = [ctypes.POINTER(Frame), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]
         L.trs_lambda_policy.restype = S
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.trs_ra_schedule.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, i32p, i32p]
+        L.trs_ra_schedule.restype = S
         L.trs_profile_read_batch.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.trs_profile_read_batch.restype = S
         L.trs_batch_create.argtypes = [ctypes.POINTER(BatchFrame), ctypes.c_int32, ctypes.c_int32,
@@ -253,6 +256,19 @@ def trs_lambda_policy(frame: Frame, n_threads: int) -> tuple[int, int]:
     check(lib().trs_lambda_policy(ctypes.byref(frame), n_threads, ctypes.byref(num), ctypes.byref(den)),
           "trs_lambda_policy")
     return num.value, den.value
+
+
+def trs_ra_schedule(gop_size: int, n_frames: int) -> dict:
+    """Random-access GOP bookkeeping: coding order, temporal layer per frame, and per frame
+    the co-TL reference (previously coded frame of the same layer) and the closest coded
+    frame in display order (-1 where none exists)."""
+    import numpy as np
+    out = {k: np.zeros(max(n_frames, 1), np.int32)
+           for k in ("coding_order", "layer", "cotl_ref", "closest_ref")}
+    ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    check(lib().trs_ra_schedule(gop_size, n_frames, ptr(out["coding_order"]), ptr(out["layer"]),
+                                ptr(out["cotl_ref"]), ptr(out["closest_ref"])), "trs_ra_schedule")
+    return out
 
 
 def trs_release_plans() -> None:

@@ -374,3 +374,16 @@ def test_idle_threads_on_a_frame_smaller_than_n(orc):
         assert o["n_enumerated"] == b["n_enumerated"] == size
         assert (o["rank"], o["t_min"], o["q_sel"], o["rs"]) == (b["rank"], b["t_min"], b["q_sel"], b["rs"])
         assert o["n_rs"] == 6
+
+
+@pytest.mark.parametrize("lam", LAMS)
+def test_decision_is_invariant_to_scaling_the_time_map(orc, lam):
+    """Multiplying every predicted CTU time by the same integer scales T~min, the Eq. 4 bound
+    and every T~(P) alike and leaves Q alone, so the chosen partition does not change."""
+    w, h = 1920, 1080
+    luma, f, cost = _inputs(orc, w, h, 13)
+    p = orc.make_params(4, 3, 3, 2, lam=lam)
+    a = orc.search(w, h, p, cost, f["s1"], f["s2"])
+    b = orc.search(w, h, p, (np.asarray(cost, np.uint32) * 7).astype(np.uint32), f["s1"], f["s2"])
+    assert (b["rank"], b["rs"], b["q_sel"]) == (a["rank"], a["rs"], a["q_sel"])
+    assert (b["t_min"], b["t_sel"]) == (7 * a["t_min"], 7 * a["t_sel"])
