@@ -71,6 +71,7 @@ def lib():
                                      ctypes.POINTER(ctypes.c_int32)]
         L.orc_search.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(OrcParams),
                                  P, P, P, ctypes.POINTER(OrcResult)]
+        L.orc_literal_search.argtypes = L.orc_search.argtypes
         _lib = L
     return _lib
 
@@ -136,6 +137,21 @@ def search(w: int, h: int, params: OrcParams, cost: np.ndarray, s1: np.ndarray,
                           ctypes.byref(res))
     if rc < 0:
         raise ValueError(f"orc_search failed: {rc}")
+    return result_dict(res)
+
+
+def literal_search(w: int, h: int, params: OrcParams, cost: np.ndarray, s1: np.ndarray,
+                   s2: np.ndarray, cs: int = 128) -> dict:
+    """Exact two-step search over the literal space (every CTU boundary allowed) by the
+    window / tile / strip / column decomposition; rank and n_feasible are -1."""
+    cost = np.ascontiguousarray(cost, dtype=np.uint32)
+    s1 = np.ascontiguousarray(s1, dtype=np.uint32)
+    s2 = np.ascontiguousarray(s2, dtype=np.uint64)
+    res = OrcResult()
+    rc = lib().orc_literal_search(w, h, cs, ctypes.byref(params), _ptr(cost), _ptr(s1), _ptr(s2),
+                                  ctypes.byref(res))
+    if rc < 0:
+        raise ValueError(f"orc_literal_search failed: {rc}")
     return result_dict(res)
 
 

@@ -16,6 +16,9 @@
  *   - step 2: among partitions with T~(P) <= T~min (1 + lambda), the one minimising the
  *     within-region luma sum of squared errors;                   (Eq. 2 and Eq. 4)
  *   - both steps search only partitions with k * A_min(P) > A_max(P), k = 3.  (Section 2.3)
+ *   - the same two steps over the literal space (every CTU boundary allowed), solved exactly
+ *     by decomposition instead of enumeration (orc_literal_search; pinned to the exhaustive
+ *     search of that space where it finishes).
  *
  * Readings of points the paper leaves open (each is also listed in the design notes):
  *   - the number of rectangular slices (RS) equals the thread count N;
@@ -646,5 +649,454 @@ int orc_search(int w, int h, int cs, const orc_params *p, const uint32_t *cost,
     }
     out->status = rc;
     free(s.colpx); free(s.rowpx); free(s.satT); free(s.satS1); free(s.satS2);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------- */
+/* Exact two-step search over the literal space, by decomposition.                      */
+/* ------------------------------------------------------------------------------------- */
+/*
+ * The literal space lets every CTU boundary serve as a tile boundary and as a split row
+ * (dt = dr = unbounded); otherwise as above: c <= Cmax, r <= Rmax, k_t in [1, min(Kmax, h_t)],
+ * sum of k_t = N.  At 4K it holds 5.4e9 candidates, so instead of listing them the two steps
+ * are solved exactly by splitting the problem:
+ *
+ *  - Area rule (Section 2.3): P passes iff every RS area lies in [a, k a) for a = A_min(P).
+ *    So the feasible set is the union over a of the sets whose RS areas all lie in the window
+ *    [a, k a), with a running over the distinct RS areas such that N a <= A_total < k N a
+ *    (N areas in such a window could not add up to the frame otherwise).  With the window
+ *    fixed, the rule is a condition on each RS alone.  k = 0 (rule off): one window, no bound.
+ *  - Step 1 (Eq. 1, Eq. 3): with a window and the row boundaries Y fixed, the largest RS time
+ *    is a maximum over tiles of a maximum over their slices.  Per tile rectangle and slice
+ *    count k: the least possible largest slice time (a DP over the split rows).  Per column
+ *    strip and RS count K: the least largest time of the strip's r tiles holding K slices in
+ *    all (a DP over the tiles).  Then a DP over the column boundaries whose state is
+ *    (tile columns used, RS used).  T~min is the least result over windows, r and Y.
+ *  - Step 2 (Eq. 2 under Eq. 4): tau = floor(T~min (den + num) / den) bounds every RS time,
+ *    a condition on each RS alone again, and Q is a sum over RS; the same three DPs then
+ *    minimise (Q, T~(P)) lexicographically: sums and maxima both compose monotonically.
+ * Ties: the first in the order (window ascending, r ascending, Y lexicographic, c ascending),
+ * and inside the DPs the first minimising choice in ascending loop order.  The canonical rank
+ * is not computed (-1) and n_feasible is not counted (-1).
+ */
+
+typedef struct { int64_t q, t; } lexv;          /* (Q, T~) of step 2; q = INT64_MAX: none */
+
+static const int64_t LIT_INF = INT64_MAX;
+
+typedef struct {
+    int W, H, N, Cm, Rm, Km;
+    int64_t *colpx, *rowpx, *satT, *satS1, *satS2;
+    /* per rectangle (x0, x1, y0, y1): area, time, q = S2 - floor(S1^2 / n) */
+    int64_t *A, *T, *Q;
+    /* tile tables for the current window: [rect][k], k = 1..Km */
+    int64_t *t1;
+    lexv *t2;
+    int64_t lo, hi;                 /* window [lo, hi); hi = LIT_INF when the rule is off */
+    int64_t tau;                    /* step-2 bound on RS times */
+} lit_ctx;
+
+static size_t lit_rect(const lit_ctx *L, int x0, int x1, int y0, int y1)
+{
+    return (((size_t)x0 * (L->W + 1) + x1) * (L->H + 1) + y0) * (L->H + 1) + y1;
+}
+
+static int lit_ok(const lit_ctx *L, size_t r)
+{
+    return L->A[r] >= L->lo && L->A[r] < L->hi;
+}
+
+static lexv lex_join(lexv a, lexv b)       /* regions side by side: Q adds, T~ takes the max */
+{
+    lexv o;
+    if (a.q == LIT_INF || b.q == LIT_INF) { o.q = LIT_INF; o.t = LIT_INF; return o; }
+    o.q = a.q + b.q;
+    o.t = a.t > b.t ? a.t : b.t;
+    return o;
+}
+
+static int lex_less(lexv a, lexv b)
+{
+    return a.q < b.q || (a.q == b.q && a.t < b.t);
+}
+
+/* Tile tables for the current window (and, for step 2, tau): for every tile rectangle and k,
+ * the best split of its rows into k slices, each slice an RS passing the per-RS conditions.
+ * If choice is given (step 2 only, one rectangle), it receives the split rows of the best. */
+static void lit_tile_dp(lit_ctx *L, int step, int x0, int x1, int y0,
+                        int64_t f1[][ORC_MAXB], lexv f2[][ORC_MAXB], int arg[][ORC_MAXB])
+{
+    const int H = L->H, Km = L->Km;
+    for (int q = 0; q <= Km; q++)
+        for (int y = 0; y <= H; y++) {
+            f1[q][y] = LIT_INF;
+            f2[q][y].q = LIT_INF; f2[q][y].t = LIT_INF;
+            arg[q][y] = -1;
+        }
+    f1[0][y0] = 0;
+    f2[0][y0].q = 0; f2[0][y0].t = 0;
+    for (int q = 1; q <= Km; q++)
+        for (int y = y0 + q; y <= H; y++)
+            for (int yp = y0 + q - 1; yp < y; yp++) {
+                size_t r = lit_rect(L, x0, x1, yp, y);
+                if (!lit_ok(L, r)) continue;
+                if (step == 1) {
+                    if (f1[q - 1][yp] == LIT_INF) continue;
+                    int64_t v = f1[q - 1][yp] > L->T[r] ? f1[q - 1][yp] : L->T[r];
+                    if (v < f1[q][y]) { f1[q][y] = v; arg[q][y] = yp; }
+                } else {
+                    if (L->T[r] > L->tau) continue;
+                    lexv s = { L->Q[r], L->T[r] };
+                    lexv v = lex_join(f2[q - 1][yp], s);
+                    if (v.q != LIT_INF && lex_less(v, f2[q][y])) { f2[q][y] = v; arg[q][y] = yp; }
+                }
+            }
+}
+
+static void lit_tables(lit_ctx *L, int step)
+{
+    int64_t (*f1)[ORC_MAXB] = malloc(sizeof(int64_t) * ORC_MAXB * ORC_MAXB);
+    lexv (*f2)[ORC_MAXB] = malloc(sizeof(lexv) * ORC_MAXB * ORC_MAXB);
+    int (*arg)[ORC_MAXB] = malloc(sizeof(int) * ORC_MAXB * ORC_MAXB);
+    for (int x0 = 0; x0 < L->W; x0++)
+        for (int x1 = x0 + 1; x1 <= L->W; x1++)
+            for (int y0 = 0; y0 < L->H; y0++) {
+                lit_tile_dp(L, step, x0, x1, y0, f1, f2, arg);
+                for (int y1 = y0 + 1; y1 <= L->H; y1++)
+                    for (int k = 1; k <= L->Km; k++) {
+                        size_t r = lit_rect(L, x0, x1, y0, y1) * (size_t)L->Km + (k - 1);
+                        if (step == 1) L->t1[r] = f1[k][y1];
+                        else L->t2[r] = f2[k][y1];
+                    }
+            }
+    free(f1); free(f2); free(arg);
+}
+
+/* Best RS count split over the r tiles of column strip [x0, x1) with rows Y: out[K] for K
+ * slices in the strip (K = 0..N); kk (optional) receives the per-tile counts for K = want. */
+static void lit_strip(const lit_ctx *L, int step, int x0, int x1, int r, const int *Y,
+                      int64_t *o1, lexv *o2, int want, int *kk)
+{
+    const int N = L->N, Km = L->Km;
+    int64_t u1[ORC_MAXB][ORC_MAXN + 1];
+    lexv u2[ORC_MAXB][ORC_MAXN + 1];
+    int ch[ORC_MAXB][ORC_MAXN + 1];
+    for (int K = 0; K <= N; K++) { u1[0][K] = LIT_INF; u2[0][K].q = LIT_INF; u2[0][K].t = LIT_INF; }
+    u1[0][0] = 0;
+    u2[0][0].q = 0; u2[0][0].t = 0;
+    for (int j = 0; j < r; j++) {
+        size_t base = lit_rect(L, x0, x1, Y[j], Y[j + 1]) * (size_t)Km;
+        for (int K = 0; K <= N; K++) {
+            u1[j + 1][K] = LIT_INF;
+            u2[j + 1][K].q = LIT_INF; u2[j + 1][K].t = LIT_INF;
+            ch[j + 1][K] = 0;
+            for (int k = 1; k <= Km && k <= K; k++) {
+                if (step == 1) {
+                    int64_t a = u1[j][K - k], b = L->t1[base + k - 1];
+                    if (a == LIT_INF || b == LIT_INF) continue;
+                    int64_t v = a > b ? a : b;
+                    if (v < u1[j + 1][K]) { u1[j + 1][K] = v; ch[j + 1][K] = k; }
+                } else {
+                    lexv v = lex_join(u2[j][K - k], L->t2[base + k - 1]);
+                    if (v.q != LIT_INF && lex_less(v, u2[j + 1][K])) { u2[j + 1][K] = v; ch[j + 1][K] = k; }
+                }
+            }
+        }
+    }
+    for (int K = 0; K <= N; K++) {
+        if (o1) o1[K] = u1[r][K];
+        if (o2) o2[K] = u2[r][K];
+    }
+    if (kk)
+        for (int j = r, K = want; j > 0; j--) { kk[j - 1] = ch[j][K]; K -= ch[j][K]; }
+}
+
+/* Column DP for fixed window and Y.  best1[c] / best2[c]: best over c tile columns (c = 1..Cm).
+ * If cx / ck are given (step 2, target c = want_c), they receive the column boundaries and
+ * per-strip RS counts of the best. */
+static void lit_columns(const lit_ctx *L, int step, int r, const int *Y, int64_t *best1,
+                        lexv *best2, int want_c, int *cx, int *ck)
+{
+    const int W = L->W, N = L->N, Cm = L->Cm;
+    const size_t S = (size_t)(W + 1) * (W + 1) * (N + 1);
+    int64_t *h1 = malloc(sizeof(int64_t) * S);
+    lexv *h2 = malloc(sizeof(lexv) * S);
+    for (int x0 = 0; x0 < W; x0++)
+        for (int x1 = x0 + 1; x1 <= W; x1++) {
+            size_t o = ((size_t)x0 * (W + 1) + x1) * (N + 1);
+            lit_strip(L, step, x0, x1, r, Y, h1 + o, h2 + o, 0, NULL);
+        }
+    const size_t F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    int64_t *F1 = malloc(sizeof(int64_t) * F);
+    lexv *F2 = malloc(sizeof(lexv) * F);
+    int *AX = malloc(sizeof(int) * F), *AK = malloc(sizeof(int) * F);
+#define FI(i, x, n) (((size_t)(i) * (W + 1) + (x)) * (N + 1) + (n))
+    for (size_t e = 0; e < F; e++) { F1[e] = LIT_INF; F2[e].q = LIT_INF; F2[e].t = LIT_INF; AX[e] = AK[e] = -1; }
+    F1[FI(0, 0, 0)] = 0;
+    F2[FI(0, 0, 0)].q = 0; F2[FI(0, 0, 0)].t = 0;
+    for (int i = 1; i <= Cm; i++)
+        for (int x = i; x <= W; x++)
+            for (int n = 1; n <= N; n++)
+                for (int xp = i - 1; xp < x; xp++)
+                    for (int K = 1; K <= n; K++) {
+                        size_t hp = ((size_t)xp * (W + 1) + x) * (N + 1) + K, fp = FI(i - 1, xp, n - K);
+                        if (step == 1) {
+                            if (F1[fp] == LIT_INF || h1[hp] == LIT_INF) continue;
+                            int64_t v = F1[fp] > h1[hp] ? F1[fp] : h1[hp];
+                            if (v < F1[FI(i, x, n)]) { F1[FI(i, x, n)] = v; AX[FI(i, x, n)] = xp; AK[FI(i, x, n)] = K; }
+                        } else {
+                            lexv v = lex_join(F2[fp], h2[hp]);
+                            if (v.q != LIT_INF && lex_less(v, F2[FI(i, x, n)])) {
+                                F2[FI(i, x, n)] = v; AX[FI(i, x, n)] = xp; AK[FI(i, x, n)] = K;
+                            }
+                        }
+                    }
+    for (int c = 1; c <= Cm; c++) {
+        if (best1) best1[c] = F1[FI(c, W, N)];
+        if (best2) best2[c] = F2[FI(c, W, N)];
+    }
+    if (cx) {
+        int x = W, n = N;
+        cx[want_c] = W;
+        for (int i = want_c; i > 0; i--) {
+            int xp = AX[FI(i, x, n)], K = AK[FI(i, x, n)];
+            cx[i - 1] = xp;
+            ck[i - 1] = K;
+            x = xp;
+            n -= K;
+        }
+    }
+#undef FI
+    free(h1); free(h2); free(F1); free(F2); free(AX); free(AK);
+}
+
+/* Next increasing vector Y (Y[0] = 0, Y[r] = H) in lexicographic order; 0 when done. */
+static int lit_next_y(int *Y, int r, int H)
+{
+    for (int j = r - 1; j >= 1; j--) {
+        if (Y[j] < H - (r - j)) {
+            Y[j]++;
+            for (int q = j + 1; q < r; q++) Y[q] = Y[q - 1] + 1;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+int orc_literal_search(int w, int h, int cs, const orc_params *p, const uint32_t *cost,
+                       const uint32_t *s1, const uint64_t *s2, orc_result *out)
+{
+    memset(out, 0, sizeof(*out));
+    if (w <= 0 || h <= 0 || cs <= 0 || !p) return -1;
+    const int W = (w + cs - 1) / cs, H = (h + cs - 1) / cs;
+    if (W > 64 || H > 64 || p->n_threads < 1 || p->n_threads > ORC_MAXN || p->max_tile_cols < 1 ||
+        p->max_tile_rows < 1 || p->max_rs_per_tile < 1 || p->lambda_den < 1 || p->area_k < 0 ||
+        p->prune != 0 || (p->min_rs != 0 && p->min_rs != p->n_threads))
+        return -1;
+    lit_ctx L;
+    memset(&L, 0, sizeof(L));
+    L.W = W; L.H = H; L.N = p->n_threads;
+    L.Cm = p->max_tile_cols < W ? p->max_tile_cols : W;
+    L.Rm = p->max_tile_rows < H ? p->max_tile_rows : H;
+    L.Km = p->max_rs_per_tile < H ? p->max_rs_per_tile : H;
+    L.colpx = calloc((size_t)W + 1, sizeof(int64_t));
+    L.rowpx = calloc((size_t)H + 1, sizeof(int64_t));
+    for (int x = 1; x <= W; x++) L.colpx[x] = L.colpx[x - 1] + (x * cs <= w ? cs : w - (x - 1) * cs);
+    for (int y = 1; y <= H; y++) L.rowpx[y] = L.rowpx[y - 1] + (y * cs <= h ? cs : h - (y - 1) * cs);
+    int64_t *vt = malloc(sizeof(int64_t) * (size_t)W * H);
+    int64_t *v1 = malloc(sizeof(int64_t) * (size_t)W * H);
+    int64_t *v2 = malloc(sizeof(int64_t) * (size_t)W * H);
+    for (int64_t c = 0; c < (int64_t)W * H; c++) { vt[c] = cost[c]; v1[c] = s1[c]; v2[c] = (int64_t)s2[c]; }
+    size_t satn = (size_t)(W + 1) * (H + 1);
+    L.satT = malloc(sizeof(int64_t) * satn);
+    L.satS1 = malloc(sizeof(int64_t) * satn);
+    L.satS2 = malloc(sizeof(int64_t) * satn);
+    build_sat(W, H, vt, L.satT);
+    build_sat(W, H, v1, L.satS1);
+    build_sat(W, H, v2, L.satS2);
+    free(vt); free(v1); free(v2);
+
+    /* every rectangle: area, time, q */
+    const size_t nrect = (size_t)(W + 1) * (W + 1) * (H + 1) * (H + 1);
+    L.A = calloc(nrect, sizeof(int64_t));
+    L.T = calloc(nrect, sizeof(int64_t));
+    L.Q = calloc(nrect, sizeof(int64_t));
+    int64_t *areas = malloc(sizeof(int64_t) * nrect);
+    size_t n_areas = 0;
+    for (int x0 = 0; x0 < W; x0++)
+        for (int x1 = x0 + 1; x1 <= W; x1++)
+            for (int y0 = 0; y0 < H; y0++)
+                for (int y1 = y0 + 1; y1 <= H; y1++) {
+                    size_t r = lit_rect(&L, x0, x1, y0, y1);
+                    int64_t A = (L.colpx[x1] - L.colpx[x0]) * (L.rowpx[y1] - L.rowpx[y0]);
+                    int64_t S1 = rect_sum(L.satS1, W, x0, y0, x1, y1);
+                    int64_t S2 = rect_sum(L.satS2, W, x0, y0, x1, y1);
+                    L.A[r] = A;
+                    L.T[r] = rect_sum(L.satT, W, x0, y0, x1, y1);
+                    L.Q[r] = S2 - (int64_t)(((__int128)S1 * S1) / A);
+                    areas[n_areas++] = A;
+                }
+    /* windows */
+    const int64_t Atot = L.colpx[W] * L.rowpx[H], N = L.N, k = p->area_k;
+    int64_t *win = malloc(sizeof(int64_t) * (n_areas + 1));
+    size_t n_win = 0;
+    if (k == 0) {
+        win[n_win++] = 0;
+    } else {
+        qsort(areas, n_areas, sizeof(int64_t), cmp_i64);
+        for (size_t i = 0; i < n_areas; i++) {
+            if (i > 0 && areas[i] == areas[i - 1]) continue;
+            if (N * areas[i] <= Atot && (__int128)k * N * areas[i] > Atot) win[n_win++] = areas[i];
+        }
+    }
+    free(areas);
+    L.t1 = malloc(sizeof(int64_t) * nrect * L.Km);
+    L.t2 = malloc(sizeof(lexv) * nrect * L.Km);
+
+    int64_t cnt;
+    int32_t dtu, dru;
+    orc_params lp = *p;
+    lp.dtile = -1; lp.drs = -1;
+    orc_space_size(W, H, &lp, &cnt, &dtu, &dru);
+    out->n_enumerated = cnt;
+    out->n_feasible = -1;
+    out->rank = -1;
+    out->uniform_rank = -1;
+    out->dtile_used = -1;
+    out->drs_used = -1;
+
+    /* step 1 */
+    int64_t tmin = LIT_INF, best1[ORC_MAXB];
+    int Y[ORC_MAXB];
+    for (size_t wi = 0; wi < n_win; wi++) {
+        L.lo = win[wi];
+        L.hi = k == 0 ? LIT_INF : k * win[wi];
+        lit_tables(&L, 1);
+        for (int r = 1; r <= L.Rm; r++) {
+            for (int j = 0; j < r; j++) Y[j] = j;
+            Y[r] = H;
+            do {
+                lit_columns(&L, 1, r, Y, best1, NULL, 0, NULL, NULL);
+                for (int c = 1; c <= L.Cm; c++) if (best1[c] < tmin) tmin = best1[c];
+            } while (lit_next_y(Y, r, H));
+        }
+    }
+    /* the uniform grid (Section 3.2), reported and returned when nothing is feasible */
+    int cu, ru = 1;
+    for (int d = 1; (int64_t)d * d <= N; d++) if (N % d == 0) ru = d;
+    cu = (int)N / ru;
+    int64_t ut = -1, uq = -1;
+    if (cu <= W && ru <= H) {
+        ut = 0; uq = 0;
+        for (int j = 0; j < ru; j++)
+            for (int i = 0; i < cu; i++) {
+                size_t rr = lit_rect(&L, (int)((int64_t)i * W / cu), (int)((int64_t)(i + 1) * W / cu),
+                                     (int)((int64_t)j * H / ru), (int)((int64_t)(j + 1) * H / ru));
+                if (L.T[rr] > ut) ut = L.T[rr];
+                uq += L.Q[rr];
+            }
+    }
+    out->t_unif = ut;
+    out->q_unif = uq;
+    int rc = 0;
+    if (tmin == LIT_INF) {
+        out->status = 1;
+        out->t_min = -1;
+        out->t_sel = ut;
+        out->q_sel = uq;
+        if (ut >= 0) {
+            int n = 0;
+            out->tile_cols = cu;
+            out->tile_rows = ru;
+            for (int i = 0; i <= cu; i++) out->col_bd[i] = (int)((int64_t)i * W / cu);
+            for (int j = 0; j <= ru; j++) out->row_bd[j] = (int)((int64_t)j * H / ru);
+            for (int j = 0; j < ru; j++)
+                for (int i = 0; i < cu; i++, n++) {
+                    out->rs[n][0] = out->col_bd[i]; out->rs[n][1] = out->row_bd[j];
+                    out->rs[n][2] = out->col_bd[i + 1]; out->rs[n][3] = out->row_bd[j + 1];
+                    out->rs_time[n] = L.T[lit_rect(&L, out->rs[n][0], out->rs[n][2], out->rs[n][1], out->rs[n][3])];
+                }
+            out->n_rs = n;
+        }
+        rc = 1;
+    } else {
+        /* step 2 */
+        L.tau = p->lambda_num < 0 ? LIT_INF
+              : (int64_t)(((__int128)tmin * (p->lambda_den + p->lambda_num)) / p->lambda_den);
+        lexv best = { LIT_INF, LIT_INF }, b2[ORC_MAXB];
+        size_t bw = 0;
+        int br = 0, bc = 0, bY[ORC_MAXB] = {0};
+        for (size_t wi = 0; wi < n_win; wi++) {
+            L.lo = win[wi];
+            L.hi = k == 0 ? LIT_INF : k * win[wi];
+            lit_tables(&L, 2);
+            for (int r = 1; r <= L.Rm; r++) {
+                for (int j = 0; j < r; j++) Y[j] = j;
+                Y[r] = H;
+                do {
+                    lit_columns(&L, 2, r, Y, NULL, b2, 0, NULL, NULL);
+                    for (int c = 1; c <= L.Cm; c++)
+                        if (b2[c].q != LIT_INF && lex_less(b2[c], best)) {
+                            best = b2[c]; bw = wi; br = r; bc = c;
+                            memcpy(bY, Y, sizeof(int) * (r + 1));
+                        }
+                } while (lit_next_y(Y, r, H));
+            }
+        }
+        /* rebuild the winner: column boundaries, per-strip counts, per-tile counts, splits */
+        L.lo = win[bw];
+        L.hi = k == 0 ? LIT_INF : k * win[bw];
+        lit_tables(&L, 2);
+        int cx[ORC_MAXB], ck[ORC_MAXB];
+        lit_columns(&L, 2, br, bY, NULL, b2, bc, cx, ck);
+        int tk[ORC_MAXB][ORC_MAXB];                   /* [column][row] slice counts */
+        for (int i = 0; i < bc; i++) {
+            int kk[ORC_MAXB];
+            lit_strip(&L, 2, cx[i], cx[i + 1], br, bY, NULL, NULL, ck[i], kk);
+            for (int j = 0; j < br; j++) tk[i][j] = kk[j];
+        }
+        int64_t (*f1)[ORC_MAXB] = malloc(sizeof(int64_t) * ORC_MAXB * ORC_MAXB);
+        lexv (*f2)[ORC_MAXB] = malloc(sizeof(lexv) * ORC_MAXB * ORC_MAXB);
+        int (*arg)[ORC_MAXB] = malloc(sizeof(int) * ORC_MAXB * ORC_MAXB);
+        int n = 0;
+        int64_t tsel = 0, qsel = 0;
+        for (int j = 0; j < br; j++)
+            for (int i = 0; i < bc; i++) {
+                lit_tile_dp(&L, 2, cx[i], cx[i + 1], bY[j], f1, f2, arg);
+                int rows[ORC_MAXB], kq = tk[i][j];
+                rows[kq] = bY[j + 1];
+                for (int q = kq, y = bY[j + 1]; q > 0; q--) { y = arg[q][y]; rows[q - 1] = y; }
+                for (int q = 0; q < kq; q++) {
+                    size_t rr = lit_rect(&L, cx[i], cx[i + 1], rows[q], rows[q + 1]);
+                    out->rs[n][0] = cx[i]; out->rs[n][1] = rows[q];
+                    out->rs[n][2] = cx[i + 1]; out->rs[n][3] = rows[q + 1];
+                    out->rs_time[n] = L.T[rr];
+                    if (L.T[rr] > tsel) tsel = L.T[rr];
+                    qsel += L.Q[rr];
+                    n++;
+                }
+            }
+        free(f1); free(f2); free(arg);
+        out->n_rs = n;
+        out->tile_cols = bc;
+        out->tile_rows = br;
+        for (int i = 0; i <= bc; i++) out->col_bd[i] = cx[i];
+        for (int j = 0; j <= br; j++) out->row_bd[j] = bY[j];
+        out->t_min = tmin;
+        out->t_sel = tsel;
+        out->q_sel = qsel;
+        out->status = 0;
+        /* the rebuilt partition must score what the DP promised */
+        if (tsel != best.t || qsel != best.q) rc = -2;
+    }
+    free(win);
+    free(L.colpx); free(L.rowpx); free(L.satT); free(L.satS1); free(L.satS2);
+    free(L.A); free(L.T); free(L.Q); free(L.t1); free(L.t2);
     return rc;
 }
