@@ -180,6 +180,29 @@ trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
                       void *workspace, size_t ws_bytes, trs_result *out_dev,
                       hipStream_t stream);
 
+/* Exact two-step search over the literal space, in which every CTU boundary may be a tile
+ * boundary and a split row (the space of Section 2.3 without windows: params->dtile and
+ * params->drs must both be -1).  Same decision rule as trs_search (Eq. 3, then Eq. 2 under
+ * Eq. 4, area rule of Section 2.3), solved without listing the candidates: the area rule is
+ * split into windows [a, k a) over the possible smallest RS areas a, and inside a window the
+ * least largest RS time and the least (Q, T~(P)) follow from dynamic programs over split rows,
+ * tiles and column boundaries.  Among partitions with equal (Q, T~(P)) it returns the first in
+ * the order (window, r, row boundaries, c) of that decomposition, not the smallest canonical
+ * rank: rank, n_feasible and uniform_rank are -1, n_step2 is the number of (window, row
+ * boundaries) units, n_enumerated the size of the literal space; status in the result is
+ * TRS_ENOFEASIBLE (uniform grid returned) when nothing passes the area rule.  Inputs as in
+ * trs_search; workspace: device, at least trs_literal_workspace() bytes, 256-byte aligned.
+ * Limits: W <= 64 and H <= 40 CTUs, N <= 32, at most 2^24 units, and LDS tables within 64 KB
+ * (TRS_ENOTIMPL / TRS_ENOSPACE beyond); prune must be 0 and min_rs 0 or N (TRS_ENOTIMPL).
+ * Returns TRS_OK once enqueued.  Errors: TRS_EINVAL, TRS_ENOTIMPL, TRS_ENOSPACE,
+ * TRS_EWORKSPACE, TRS_EDEVICE. */
+trs_status trs_literal_workspace(const trs_frame *frame, const trs_search_params *params,
+                                 size_t *bytes);
+trs_status trs_literal_search(const trs_frame *frame, const trs_search_params *params,
+                              const uint32_t *cost, const uint32_t *s1, const uint64_t *s2,
+                              void *workspace, size_t ws_bytes, trs_result *out_dev,
+                              hipStream_t stream);
+
 /* The whole per-frame path in one call (Fig. 3 of the paper: current-frame luma and the
  * co-located previous times in, partition out): trs_features, trs_cost_map and trs_search
  * enqueued on one stream, with the cost map fused into the prefix-sum kernel when the CTU

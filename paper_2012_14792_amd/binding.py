@@ -110,6 +110,10 @@ def lib():
         L.trs_search.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams), P, P, P, P,
                                  ctypes.c_size_t, P, P]
         L.trs_search.restype = S
+        L.trs_literal_workspace.argtypes = L.trs_search_workspace.argtypes
+        L.trs_literal_workspace.restype = S
+        L.trs_literal_search.argtypes = L.trs_search.argtypes
+        L.trs_literal_search.restype = S
         L.trs_partition.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams), P,
                                     ctypes.c_int64, P, Blend, Feat, P, P, P, ctypes.c_size_t, P, P]
         L.trs_partition.restype = S
@@ -340,6 +344,21 @@ def trs_search(frame: Frame, params: SearchParams, cost, s1, s2, workspace, out,
     check(lib().trs_search(ctypes.byref(frame), ctypes.byref(params), _ptr(cost), _ptr(s1), _ptr(s2),
                            _ptr(workspace), workspace.numel() * workspace.element_size(),
                            _ptr(out), _stream(stream)), "trs_search")
+    return out
+
+
+def trs_literal_workspace(frame: Frame, params: SearchParams) -> int:
+    n = ctypes.c_size_t()
+    check(lib().trs_literal_workspace(ctypes.byref(frame), ctypes.byref(params), ctypes.byref(n)),
+          "trs_literal_workspace")
+    return n.value
+
+
+def trs_literal_search(frame: Frame, params: SearchParams, cost, s1, s2, workspace, out, stream=None):
+    """Enqueue the exact search over the literal space (params.dtile = params.drs = -1)."""
+    check(lib().trs_literal_search(ctypes.byref(frame), ctypes.byref(params), _ptr(cost), _ptr(s1),
+                                   _ptr(s2), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                   _ptr(out), _stream(stream)), "trs_literal_search")
     return out
 
 

@@ -23,8 +23,8 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-function"]
 
-SOURCES = [("kernels.hip", True), ("mlp.hip", True), ("space.cpp", False), ("gop.cpp", False),
-           ("api.cpp", True)]
+SOURCES = [("kernels.hip", True), ("mlp.hip", True), ("literal.hip", True), ("space.cpp", False),
+           ("gop.cpp", False), ("api.cpp", True)]
 
 
 def build(verbose: bool = False) -> str:

@@ -16,6 +16,12 @@
 #include "space.hpp"
 #include "trs.h"
 
+namespace trs {
+namespace lit {
+void release_all();   // literal-space plans (literal.hip)
+}
+}  // namespace trs
+
 namespace {
 
 using trs::Plan;
@@ -749,6 +755,7 @@ trs_status trs_mlp_cost(const trs_frame *frame, const float *y, const float *x,
 
 void trs_release_plans(void)
 {
+    trs::lit::release_all();
     std::lock_guard<std::mutex> lk(g_mu);
     g_generation.fetch_add(1, std::memory_order_acq_rel);
     for (auto &kv : g_plans)

@@ -14,6 +14,8 @@
 
 #include <climits>
 
+#include "intmath.hpp"
+
 namespace trs {
 namespace {
 
@@ -435,19 +437,6 @@ __device__ __forceinline__ long long rect(const long long *__restrict__ sat, int
                                           int x1, int y1)
 {
     return sat[y1 * S + x1] - sat[y0 * S + x1] - sat[y1 * S + x0] + sat[y0 * S + x0];
-}
-
-// floor(s1^2 / n) for 0 <= s1 < 2^38 and 1 <= n < 2^27.  The quotient is at most the
-// region's sum of squares (< 2^50), so a double estimate is within one unit; the exact
-// remainder in wrapping 64-bit arithmetic corrects it.
-__device__ __forceinline__ unsigned long long floor_sq_div(unsigned long long s1, unsigned n)
-{
-    const double d = (double)s1;
-    unsigned long long q = (unsigned long long)((d * d) / (double)n);
-    long long rem = (long long)(s1 * s1 - q * (unsigned long long)n);
-    while (rem < 0) { q--; rem += n; }
-    while (rem >= (long long)n) { q++; rem -= n; }
-    return q;
 }
 
 __device__ __forceinline__ int kcnt(const SpaceView &sp, int h, int kk)

@@ -1,0 +1,848 @@
+// Exact two-step search over the literal candidate space: every CTU boundary may serve as a
+// tile boundary and as a split row (the space of Section 2.3 with no window around the uniform
+// positions).  At 4K it holds 5.4e9 candidates, so instead of scoring them one by one the
+// search is split into exact parts:
+//
+//   area windows  a partition passes the area rule k A_min > A_max iff all its RS areas lie in
+//                 [a, k a) for a = its smallest area; the feasible set is the union over the
+//                 windows [a, k a), a running over the distinct RS areas with
+//                 N a <= A_total < k N a (host-side list); inside a window the rule is a
+//                 condition on each RS alone;
+//   k_lit_tiles   per (window, column strip): for every row range and slice count k, the best
+//                 split of the tile's rows into k slices, one DP level per k (step 1: least
+//                 largest slice time, Eq. 1; step 2: least (Q, T~) with every slice time
+//                 within the Eq. 4 bound);
+//   k_lit_units   per (window, row boundaries Y): a DP over column boundaries whose state is
+//                 (tile columns used, RS used); the value of a column strip holding K RS comes
+//                 from a DP over its r tiles.  One wave per unit, a wavefront over the right
+//                 edge x of the strips, all state in LDS;
+//   k_lit_pick    the best unit: step 1 by an atomic minimum of T~min, step 2 by a reduction
+//                 over (Q, T~(P), unit);
+//   k_lit_final   one wave redoes the winning unit keeping the argmins, rebuilds boundaries
+//                 and splits, and writes the trs_result.
+// Ties follow the order (window, r, Y lexicographic, c) and the first minimising choice in
+// ascending loop order inside each DP.  The canonical rank is not computed (-1), nor the count
+// of feasible candidates (-1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "intmath.hpp"
+#include "space.hpp"
+#include "trs.h"
+
+namespace trs {
+namespace lit {
+namespace {
+
+constexpr long long kInf = LLONG_MAX;
+constexpr unsigned long long kNone = ~0ull;
+constexpr int kMaxW = 64, kMaxH = 40, kMaxN = 32;
+constexpr size_t kLdsLimit = 64 * 1024;
+constexpr long long kUnitCap = 1ll << 24;
+
+// Device view of the host tables (by value).
+struct LitView {
+    int W, H, N, Cm, Rm, Km, S, R2, n_win, nY, n_units, karea, lam_num, lam_den, yrow, pad;
+    long long n_enumerated;
+    const int *colpx, *rowpx;           // pixel prefix sums
+    const long long *win;               // window lower bounds a (upper bound k a, or none)
+    const unsigned char *ytab;          // per Y: r, then Y_0 .. Y_r (yrow bytes per entry)
+    const unsigned char *strip_xy;      // per strip: x0, x1
+    const unsigned char *row_yy;        // per row pair: y0, y1
+};
+
+struct LitWs {
+    unsigned long long *hdr;            // [0] T~min, [1] winning unit, [2] its column count
+    long long *sat;                     // 3 inclusive prefix sums, (H + 1) x (W + 1) each
+    long long *rA, *rT, *rQ;            // per rectangle [S][R2]: area, time, q
+    long long *tT, *tQ;                 // per [window][strip][row pair][k - 1]
+    long long *uQ, *uT;                 // per unit: best (Q, T~) of step 2
+    int *uC;                            // per unit: its column count
+};
+
+__host__ __device__ __forceinline__ int sidx(int x0, int x1, int W)
+{
+    return x0 * W - x0 * (x0 - 1) / 2 + (x1 - x0 - 1);
+}
+
+__host__ __device__ __forceinline__ int ridx(int y0, int y1, int H)
+{
+    return y0 * H - y0 * (y0 - 1) / 2 + (y1 - y0 - 1);
+}
+
+__device__ __forceinline__ unsigned long long eq4_bound(unsigned long long tmin, int num, int den)
+{
+    if (num < 0) return kNone;
+    return tmin * (unsigned long long)(den + num) / (unsigned long long)den;
+}
+
+// Step-2 values compare by Q, then T~; step 1 by T~ alone (q stays 0).
+template <int STEP>
+__device__ __forceinline__ bool better(long long aq, long long at, long long bq, long long bt)
+{
+    if (STEP == 1) return at < bt;
+    return aq < bq || (aq == bq && at < bt);
+}
+
+// ---------------------------------------------------------------------------------------
+// Prefix sums of T~, S1, S2 (one work-group) and the header.
+__global__ void __launch_bounds__(256)
+k_lit_sat(LitView v, LitWs w, const uint32_t *__restrict__ cost, const uint32_t *__restrict__ s1,
+          const uint64_t *__restrict__ s2)
+{
+    const int W = v.W, H = v.H, P = (W + 1) * (H + 1);
+    if (threadIdx.x == 0) {
+        w.hdr[0] = kNone;
+        w.hdr[1] = kNone;
+        w.hdr[2] = 0;
+    }
+    // rows: running sums along x
+    for (int t = threadIdx.x; t < 3 * (H + 1); t += blockDim.x) {
+        const int a = t / (H + 1), y = t % (H + 1);
+        long long *row = w.sat + (size_t)a * P + (size_t)y * (W + 1);
+        long long acc = 0;
+        row[0] = 0;
+        for (int x = 1; x <= W; x++) {
+            if (y > 0) {
+                const size_t c = (size_t)(y - 1) * W + (x - 1);
+                acc += a == 0 ? (long long)cost[c] : a == 1 ? (long long)s1[c] : (long long)s2[c];
+            }
+            row[x] = acc;
+        }
+    }
+    __syncthreads();
+    // columns: running sums along y
+    for (int t = threadIdx.x; t < 3 * (W + 1); t += blockDim.x) {
+        const int a = t / (W + 1), x = t % (W + 1);
+        long long *base = w.sat + (size_t)a * P + x;
+        long long acc = 0;
+        for (int y = 0; y <= H; y++) {
+            acc += base[(size_t)y * (W + 1)];
+            base[(size_t)y * (W + 1)] = acc;
+        }
+    }
+}
+
+// Area, time and q = S2 - floor(S1^2 / n) of every rectangle.
+__global__ void __launch_bounds__(256)
+k_lit_rects(LitView v, LitWs w)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= v.S * v.R2) return;
+    const int s = i / v.R2, p = i % v.R2;
+    const int x0 = v.strip_xy[2 * s], x1 = v.strip_xy[2 * s + 1];
+    const int y0 = v.row_yy[2 * p], y1 = v.row_yy[2 * p + 1];
+    const int S = v.W + 1, P = (v.W + 1) * (v.H + 1);
+    auto rect = [&](const long long *t) {
+        return t[y1 * S + x1] - t[y0 * S + x1] - t[y1 * S + x0] + t[y0 * S + x0];
+    };
+    const long long A = (long long)(v.colpx[x1] - v.colpx[x0]) * (v.rowpx[y1] - v.rowpx[y0]);
+    const long long a1 = rect(w.sat + P), a2 = rect(w.sat + 2 * (size_t)P);
+    w.rA[i] = A;
+    w.rT[i] = rect(w.sat);
+    w.rQ[i] = a2 - (long long)floor_sq_div((unsigned long long)a1, (unsigned)A);
+}
+
+// ---------------------------------------------------------------------------------------
+// Tile tables: one work-group per (window, strip).  Threads take row pairs (y0, y); level q
+// holds the best split of rows [y0, y) into q slices.
+template <int STEP>
+__global__ void __launch_bounds__(256)
+k_lit_tiles(LitView v, LitWs w)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int R2 = v.R2, H = v.H, Km = v.Km;
+    const int wi = blockIdx.x / v.S, s = blockIdx.x % v.S;
+    long long *sA = reinterpret_cast<long long *>(lds_raw);
+    long long *sT = sA + R2;
+    long long *sQ = sT + R2;
+    long long *fT = sQ + R2;            // two levels, R2 entries each
+    long long *fQ = fT + 2 * R2;
+    unsigned long long tau = kNone;
+    if (STEP == 2) {
+        const unsigned long long tmin = w.hdr[0];
+        if (tmin == kNone) return;
+        tau = eq4_bound(tmin, v.lam_num, v.lam_den);
+    }
+    const long long lo = v.win[wi];
+    const long long hi = v.karea ? (long long)v.karea * lo : kInf;
+    const size_t rbase = (size_t)s * R2;
+    for (int p = threadIdx.x; p < R2; p += blockDim.x) {
+        sA[p] = w.rA[rbase + p];
+        sT[p] = w.rT[rbase + p];
+        if (STEP == 2) sQ[p] = w.rQ[rbase + p];
+    }
+    __syncthreads();
+    auto ok = [&](int p) {
+        return sA[p] >= lo && sA[p] < hi && (STEP == 1 || (unsigned long long)sT[p] <= tau);
+    };
+    const size_t tbase = ((size_t)wi * v.S + s) * R2;
+    for (int q = 1; q <= Km; q++) {
+        long long *curT = fT + (q & 1) * R2, *prvT = fT + ((q - 1) & 1) * R2;
+        long long *curQ = fQ + (q & 1) * R2, *prvQ = fQ + ((q - 1) & 1) * R2;
+        for (int p = threadIdx.x; p < R2; p += blockDim.x) {
+            const int y0 = v.row_yy[2 * p], y = v.row_yy[2 * p + 1];
+            long long bt = kInf, bq = kInf;
+            if (q == 1) {
+                if (ok(p)) { bt = sT[p]; bq = STEP == 2 ? sQ[p] : 0; }
+            } else {
+                for (int yp = y0 + q - 1; yp < y; yp++) {
+                    const int pp = ridx(y0, yp, H), ps = ridx(yp, y, H);
+                    if (prvT[pp] == kInf || !ok(ps)) continue;
+                    const long long t = prvT[pp] > sT[ps] ? prvT[pp] : sT[ps];
+                    const long long qq = STEP == 2 ? prvQ[pp] + sQ[ps] : 0;
+                    if (better<STEP>(qq, t, bq, bt)) { bt = t; bq = qq; }
+                }
+            }
+            curT[p] = bt;
+            if (STEP == 2) curQ[p] = bq;
+            w.tT[(tbase + p) * Km + (q - 1)] = bt;
+            if (STEP == 2) w.tQ[(tbase + p) * Km + (q - 1)] = bq;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// The column DP of one unit (window, Y) by one wave.  LDS: strip values hs[x'][K] for the
+// strips ending at the current x, the DP table F[i][x][n], and with REC the argmins.
+struct UnitLds {
+    long long *hsT, *hsQ, *FT, *FQ;
+    unsigned char *AX, *AK;
+};
+
+__host__ __device__ inline size_t unit_lds_bytes(int W, int N, int Cm, int step, bool rec)
+{
+    const size_t hs = (size_t)W * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    size_t b = 8 * (hs + F) * (step == 2 ? 2 : 1);
+    if (rec) b += 2 * F;
+    return (b + 15) & ~size_t(15);
+}
+
+__device__ inline UnitLds unit_lds(unsigned char *raw, int W, int N, int Cm, int step, bool rec)
+{
+    const size_t hs = (size_t)W * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    UnitLds L{};
+    long long *p = reinterpret_cast<long long *>(raw);
+    L.hsT = p; p += hs;
+    if (step == 2) { L.hsQ = p; p += hs; }
+    L.FT = p; p += F;
+    if (step == 2) { L.FQ = p; p += F; }
+    unsigned char *c = reinterpret_cast<unsigned char *>(p);
+    if (rec) { L.AX = c; L.AK = c + F; }
+    return L;
+}
+
+template <int STEP, bool REC>
+__device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &L, int *Yl, int &r)
+{
+    const int lane = threadIdx.x;
+    const int W = v.W, N = v.N, Cm = v.Cm, Km = v.Km, S = v.S, R2 = v.R2;
+    const int wi = u / v.nY, yi = u % v.nY;
+    const unsigned char *yt = v.ytab + (size_t)yi * v.yrow;
+    r = yt[0];
+    for (int j = lane; j <= r; j += blockDim.x) Yl[j] = yt[1 + j];
+    const size_t F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    for (size_t e = lane; e < F; e += blockDim.x) {
+        L.FT[e] = kInf;
+        if (STEP == 2) L.FQ[e] = kInf;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        L.FT[0] = 0;
+        if (STEP == 2) L.FQ[0] = 0;
+    }
+    auto fi = [&](int i, int x, int n) { return ((size_t)i * (W + 1) + x) * (N + 1) + n; };
+    for (int x = 1; x <= W; x++) {
+        // strips [x', x): DP over the r tiles, in place in row x' of hs
+        for (int xp = lane; xp < x; xp += blockDim.x) {
+            long long *hT = L.hsT + (size_t)xp * (N + 1);
+            long long *hQ = STEP == 2 ? L.hsQ + (size_t)xp * (N + 1) : nullptr;
+            for (int K = 0; K <= N; K++) {
+                hT[K] = K == 0 ? 0 : kInf;
+                if (STEP == 2) hQ[K] = K == 0 ? 0 : kInf;
+            }
+            const size_t sb = (size_t)wi * S + sidx(xp, x, W);
+            for (int j = 0; j < r; j++) {
+                const size_t tb = (sb * R2 + ridx(Yl[j], Yl[j + 1], v.H)) * Km;
+                for (int K = N; K >= 0; K--) {
+                    long long bt = kInf, bq = kInf;
+                    for (int k = 1; k <= Km && k <= K; k++) {
+                        const long long at = hT[K - k], ct = w.tT[tb + k - 1];
+                        if (at == kInf || ct == kInf) continue;
+                        const long long t = at > ct ? at : ct;
+                        const long long q = STEP == 2 ? hQ[K - k] + w.tQ[tb + k - 1] : 0;
+                        if (better<STEP>(q, t, bq, bt)) { bt = t; bq = q; }
+                    }
+                    hT[K] = bt;
+                    if (STEP == 2) hQ[K] = bq;
+                }
+            }
+        }
+        __syncthreads();
+        // states (i, n) at x
+        for (int st = lane; st < Cm * N; st += blockDim.x) {
+            const int i = 1 + st / N, n = 1 + st % N;
+            if (i > x) continue;
+            long long bt = kInf, bq = kInf;
+            int ax = -1, ak = -1;
+            for (int xp = i - 1; xp < x; xp++) {
+                const long long *hT = L.hsT + (size_t)xp * (N + 1);
+                for (int K = 1; K <= n; K++) {
+                    const size_t fp = fi(i - 1, xp, n - K);
+                    const long long at = L.FT[fp], ct = hT[K];
+                    if (at == kInf || ct == kInf) continue;
+                    const long long t = at > ct ? at : ct;
+                    const long long q = STEP == 2 ? L.FQ[fp] + L.hsQ[(size_t)xp * (N + 1) + K] : 0;
+                    if (better<STEP>(q, t, bq, bt)) { bt = t; bq = q; ax = xp; ak = K; }
+                }
+            }
+            const size_t f = fi(i, x, n);
+            L.FT[f] = bt;
+            if (STEP == 2) L.FQ[f] = bq;
+            if (REC) { L.AX[f] = (unsigned char)ax; L.AK[f] = (unsigned char)ak; }
+        }
+        __syncthreads();
+    }
+}
+
+template <int STEP>
+__global__ void __launch_bounds__(64)
+k_lit_units(LitView v, LitWs w)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int Yl[kMaxH + 1];
+    const int u = blockIdx.x;
+    if (STEP == 2 && w.hdr[0] == kNone) return;
+    const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, STEP, false);
+    int r = 0;
+    unit_dp<STEP, false>(v, w, u, L, Yl, r);
+    if (threadIdx.x != 0) return;
+    long long bt = kInf, bq = kInf;
+    int bc = 0;
+    for (int c = 1; c <= v.Cm; c++) {
+        const size_t f = ((size_t)c * (v.W + 1) + v.W) * (v.N + 1) + v.N;
+        const long long t = L.FT[f], q = STEP == 2 ? L.FQ[f] : 0;
+        if (t != kInf && better<STEP>(q, t, bq, bt)) { bt = t; bq = q; bc = c; }
+    }
+    if (STEP == 1) {
+        if (bt != kInf) atomicMin(w.hdr, (unsigned long long)bt);
+    } else {
+        w.uQ[u] = bq;
+        w.uT[u] = bt;
+        w.uC[u] = bc;
+    }
+}
+
+// Lexicographic minimum of (Q, T~, unit) over the units.
+__global__ void __launch_bounds__(1024)
+k_lit_pick(LitView v, LitWs w)
+{
+    __shared__ long long sq[1024], st[1024];
+    __shared__ int su[1024];
+    if (w.hdr[0] == kNone) return;
+    long long bq = kInf, bt = kInf;
+    int bu = INT_MAX;
+    for (int u = threadIdx.x; u < v.n_units; u += blockDim.x) {
+        const long long q = w.uQ[u], t = w.uT[u];
+        if (q == kInf) continue;
+        if (q < bq || (q == bq && (t < bt || (t == bt && u < bu)))) { bq = q; bt = t; bu = u; }
+    }
+    sq[threadIdx.x] = bq;
+    st[threadIdx.x] = bt;
+    su[threadIdx.x] = bu;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const int o = threadIdx.x + h;
+            const long long q = sq[o], t = st[o];
+            const int uu = su[o];
+            if (q < sq[threadIdx.x] || (q == sq[threadIdx.x] && (t < st[threadIdx.x] ||
+                                                              (t == st[threadIdx.x] && uu < su[threadIdx.x])))) {
+                sq[threadIdx.x] = q;
+                st[threadIdx.x] = t;
+                su[threadIdx.x] = uu;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && su[0] != INT_MAX) {
+        w.hdr[1] = (unsigned long long)su[0];
+        w.hdr[2] = (unsigned long long)w.uC[su[0]];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Rebuild the winner and write the result (one wave; lane 0 walks the argmins back).
+__host__ __device__ inline size_t final_lds_bytes(int W, int H, int N, int Cm, int Rm, int Km)
+{
+    const size_t knap = (size_t)(Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
+    return unit_lds_bytes(W, N, Cm, 2, true) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile;
+}
+
+__global__ void __launch_bounds__(64)
+k_lit_final(LitView v, LitWs w, trs_result *out)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int Yl[kMaxH + 1];
+    __shared__ __align__(16) trs_result res;
+    __shared__ int cx[kMaxW + 1], ck[kMaxW + 1];
+    __shared__ unsigned char tcnt[kMaxH][kMaxW];
+    const int lane = threadIdx.x;
+    const int W = v.W, H = v.H, N = v.N, Km = v.Km;
+    {
+        unsigned *z = reinterpret_cast<unsigned *>(&res);
+        for (size_t e = lane; e < sizeof(trs_result) / 4; e += blockDim.x) z[e] = 0;
+    }
+    const UnitLds L = unit_lds(lds_raw, W, N, v.Cm, 2, true);
+    unsigned char *extra = lds_raw + unit_lds_bytes(W, N, v.Cm, 2, true);
+    const size_t knap = (size_t)(v.Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
+    long long *kT = reinterpret_cast<long long *>(extra), *kQ = kT + knap;
+    unsigned char *kC = reinterpret_cast<unsigned char *>(kQ + knap);
+    long long *fT = reinterpret_cast<long long *>(extra + ((17 * knap + 15) & ~size_t(15)));
+    long long *fQ = fT + tile;
+    int *fA = reinterpret_cast<int *>(fQ + tile);
+    __syncthreads();
+    const unsigned long long tmin = w.hdr[0];
+    const bool feasible = tmin != kNone && w.hdr[1] != kNone;
+    int r = 0;
+    if (feasible) unit_dp<2, true>(v, w, (int)w.hdr[1], L, Yl, r);
+    if (lane == 0) {
+        auto rect_at = [&](const long long *a, int x0, int x1, int y0, int y1) {
+            return a[(size_t)sidx(x0, x1, W) * v.R2 + ridx(y0, y1, H)];
+        };
+        res.rank = -1;
+        res.n_enumerated = v.n_enumerated;
+        res.n_feasible = -1;
+        res.n_step2 = v.n_units;
+        res.uniform_rank = -1;
+        res.dtile_used = -1;
+        res.drs_used = -1;
+        // uniform grid (Section 3.2): c_u r_u = N, most square, c_u >= r_u, one RS per tile
+        int ru = 1;
+        for (int d = 1; d * d <= N; d++) if (N % d == 0) ru = d;
+        const int cu = N / ru;
+        long long ut = -1, uq = -1;
+        if (cu <= W && ru <= H) {
+            ut = 0;
+            uq = 0;
+            for (int j = 0; j < ru; j++)
+                for (int i = 0; i < cu; i++) {
+                    const int x0 = i * W / cu, x1 = (i + 1) * W / cu, y0 = j * H / ru, y1 = (j + 1) * H / ru;
+                    const long long t = rect_at(w.rT, x0, x1, y0, y1);
+                    if (t > ut) ut = t;
+                    uq += rect_at(w.rQ, x0, x1, y0, y1);
+                }
+        }
+        res.t_unif = ut;
+        res.q_unif = uq;
+        if (!feasible) {
+            res.status = TRS_ENOFEASIBLE;
+            res.t_min = -1;
+            res.t_sel = ut;
+            res.q_sel = uq;
+            if (ut >= 0) {
+                res.tile_cols = cu;
+                res.tile_rows = ru;
+                for (int i = 0; i <= cu; i++) res.col_bd[i] = i * W / cu;
+                for (int j = 0; j <= ru; j++) res.row_bd[j] = j * H / ru;
+                int n = 0;
+                for (int j = 0; j < ru; j++)
+                    for (int i = 0; i < cu; i++, n++) {
+                        res.rs[n][0] = res.col_bd[i];
+                        res.rs[n][1] = res.row_bd[j];
+                        res.rs[n][2] = res.col_bd[i + 1];
+                        res.rs[n][3] = res.row_bd[j + 1];
+                        res.rs_time[n] = rect_at(w.rT, res.rs[n][0], res.rs[n][2], res.rs[n][1], res.rs[n][3]);
+                    }
+                res.n_rs = n;
+            }
+        } else {
+            const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
+            const int wi = (int)(w.hdr[1] / (unsigned long long)v.nY), c = (int)w.hdr[2];
+            const long long lo = v.win[wi];
+            const long long hi = v.karea ? (long long)v.karea * lo : kInf;
+            auto ok = [&](int x0, int x1, int y0, int y1) {
+                const long long A = rect_at(w.rA, x0, x1, y0, y1);
+                return A >= lo && A < hi && (unsigned long long)rect_at(w.rT, x0, x1, y0, y1) <= tau;
+            };
+            // column boundaries and RS count per strip, from the column DP's argmins
+            int x = W, n = N;
+            cx[c] = W;
+            for (int i = c; i > 0; i--) {
+                const size_t f = ((size_t)i * (W + 1) + x) * (N + 1) + n;
+                cx[i - 1] = L.AX[f];
+                ck[i - 1] = L.AK[f];
+                x = cx[i - 1];
+                n -= ck[i - 1];
+            }
+            res.tile_cols = c;
+            res.tile_rows = r;
+            for (int i = 0; i <= c; i++) res.col_bd[i] = cx[i];
+            for (int j = 0; j <= r; j++) res.row_bd[j] = Yl[j];
+            // slice count of every tile of a strip: DP over its tiles, first minimising k
+            for (int i = 0; i < c; i++) {
+                const size_t sb = (size_t)wi * v.S + sidx(cx[i], cx[i + 1], W);
+                for (int K = 0; K <= N; K++) { kT[K] = K == 0 ? 0 : kInf; kQ[K] = K == 0 ? 0 : kInf; }
+                for (int j = 0; j < r; j++) {
+                    const size_t tb = (sb * v.R2 + ridx(Yl[j], Yl[j + 1], H)) * Km;
+                    for (int K = 0; K <= N; K++) {
+                        long long bt = kInf, bq = kInf;
+                        int bk = 0;
+                        for (int k = 1; k <= Km && k <= K; k++) {
+                            const long long at = kT[j * (N + 1) + K - k], ct = w.tT[tb + k - 1];
+                            if (at == kInf || ct == kInf) continue;
+                            const long long t = at > ct ? at : ct;
+                            const long long q = kQ[j * (N + 1) + K - k] + w.tQ[tb + k - 1];
+                            if (better<2>(q, t, bq, bt)) { bt = t; bq = q; bk = k; }
+                        }
+                        kT[(j + 1) * (N + 1) + K] = bt;
+                        kQ[(j + 1) * (N + 1) + K] = bq;
+                        kC[(j + 1) * (N + 1) + K] = (unsigned char)bk;
+                    }
+                }
+                for (int j = r, K = ck[i]; j > 0; j--) {
+                    tcnt[j - 1][i] = kC[j * (N + 1) + K];
+                    K -= tcnt[j - 1][i];
+                }
+            }
+            // tiles in raster order, slices top to bottom: split rows from the tile DP's argmins
+            int nrs = 0;
+            long long tsel = 0, qsel = 0;
+            for (int j = 0; j < r; j++)
+                for (int i = 0; i < c; i++) {
+                    const int kq = tcnt[j][i];
+                    const int y0 = Yl[j], y1 = Yl[j + 1], x0 = cx[i], x1 = cx[i + 1];
+                    auto at = [&](int q, int y) { return (size_t)q * (H + 1) + y; };
+                    for (int q = 0; q <= kq; q++)
+                        for (int y = y0; y <= y1; y++) { fT[at(q, y)] = kInf; fQ[at(q, y)] = kInf; fA[at(q, y)] = -1; }
+                    fT[at(0, y0)] = 0;
+                    fQ[at(0, y0)] = 0;
+                    for (int q = 1; q <= kq; q++)
+                        for (int y = y0 + q; y <= y1; y++)
+                            for (int yp = y0 + q - 1; yp < y; yp++) {
+                                if (fT[at(q - 1, yp)] == kInf || !ok(x0, x1, yp, y)) continue;
+                                const long long st = rect_at(w.rT, x0, x1, yp, y);
+                                const long long t = fT[at(q - 1, yp)] > st ? fT[at(q - 1, yp)] : st;
+                                const long long qq = fQ[at(q - 1, yp)] + rect_at(w.rQ, x0, x1, yp, y);
+                                if (better<2>(qq, t, fQ[at(q, y)], fT[at(q, y)])) {
+                                    fT[at(q, y)] = t;
+                                    fQ[at(q, y)] = qq;
+                                    fA[at(q, y)] = yp;
+                                }
+                            }
+                    int rows[kMaxH + 1];
+                    rows[kq] = y1;
+                    for (int q = kq, y = y1; q > 0; q--) { y = fA[at(q, y)]; rows[q - 1] = y; }
+                    for (int q = 0; q < kq; q++) {
+                        const long long t = rect_at(w.rT, x0, x1, rows[q], rows[q + 1]);
+                        res.rs[nrs][0] = x0;
+                        res.rs[nrs][1] = rows[q];
+                        res.rs[nrs][2] = x1;
+                        res.rs[nrs][3] = rows[q + 1];
+                        res.rs_time[nrs] = t;
+                        if (t > tsel) tsel = t;
+                        qsel += rect_at(w.rQ, x0, x1, rows[q], rows[q + 1]);
+                        nrs++;
+                    }
+                }
+            res.n_rs = nrs;
+            res.status = TRS_OK;
+            res.t_min = (long long)tmin;
+            res.t_sel = tsel;
+            res.q_sel = qsel;
+        }
+    }
+    __syncthreads();
+    const unsigned *src = reinterpret_cast<const unsigned *>(&res);
+    unsigned *dst = reinterpret_cast<unsigned *>(out);
+    for (size_t e = lane; e < sizeof(trs_result) / 4; e += blockDim.x) dst[e] = src[e];
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side: the plan (geometry, windows, row-boundary list), cached per geometry and
+// parameters with one device copy per device, and the workspace layout.
+struct LitPlan {
+    int W = 0, H = 0, N = 0, Cm = 0, Rm = 0, Km = 0, S = 0, R2 = 0, karea = 0, yrow = 0;
+    long long n_win = 0, nY = 0, n_units = 0, n_enumerated = 0;
+    std::vector<int> colpx, rowpx;
+    std::vector<long long> win;
+    std::vector<unsigned char> ytab, strip_xy, row_yy;
+    std::vector<char> blob;             // the tables above, packed for the device copy
+    size_t o_col = 0, o_row = 0, o_win = 0, o_y = 0, o_sx = 0, o_ry = 0;
+    std::map<int, void *> dev;          // device copies of the tables
+};
+
+struct WsLayout {
+    size_t hdr, sat, rA, rT, rQ, tT, tQ, uQ, uT, uC, bytes;
+};
+
+std::mutex g_mu;
+std::map<std::vector<long long>, LitPlan> g_plans;
+
+trs_status check_args(const trs_frame *f, const trs_search_params *p)
+{
+    trs_status st = check_space_args(f, p);
+    if (st != TRS_OK) return st;
+    if (p->dtile != -1 || p->drs != -1) return TRS_EINVAL;          // the literal space only
+    if (p->prune != 0 || (p->min_rs != 0 && p->min_rs != p->n_threads)) return TRS_ENOTIMPL;
+    const int W = (f->width + f->ctu_size - 1) / f->ctu_size, H = (f->height + f->ctu_size - 1) / f->ctu_size;
+    if (W > kMaxW || H > kMaxH || p->n_threads > kMaxN) return TRS_ENOTIMPL;
+    return TRS_OK;
+}
+
+trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
+{
+    const int cs = f->ctu_size;
+    pl.W = (f->width + cs - 1) / cs;
+    pl.H = (f->height + cs - 1) / cs;
+    pl.N = p->n_threads;
+    pl.Cm = std::min(p->max_tile_cols, pl.W);
+    pl.Rm = std::min(p->max_tile_rows, pl.H);
+    pl.Km = std::min(p->max_rs_per_tile, pl.H);
+    pl.karea = p->area_k;
+    pl.S = pl.W * (pl.W + 1) / 2;
+    pl.R2 = pl.H * (pl.H + 1) / 2;
+    pl.colpx.assign(pl.W + 1, 0);
+    pl.rowpx.assign(pl.H + 1, 0);
+    for (int x = 0; x < pl.W; x++) pl.colpx[x + 1] = pl.colpx[x] + std::min(cs, f->width - x * cs);
+    for (int y = 0; y < pl.H; y++) pl.rowpx[y + 1] = pl.rowpx[y] + std::min(cs, f->height - y * cs);
+    pl.strip_xy.resize(2 * (size_t)pl.S);
+    for (int x0 = 0; x0 < pl.W; x0++)
+        for (int x1 = x0 + 1; x1 <= pl.W; x1++) {
+            const int s = sidx(x0, x1, pl.W);
+            pl.strip_xy[2 * s] = (unsigned char)x0;
+            pl.strip_xy[2 * s + 1] = (unsigned char)x1;
+        }
+    pl.row_yy.resize(2 * (size_t)pl.R2);
+    for (int y0 = 0; y0 < pl.H; y0++)
+        for (int y1 = y0 + 1; y1 <= pl.H; y1++) {
+            const int q = ridx(y0, y1, pl.H);
+            pl.row_yy[2 * q] = (unsigned char)y0;
+            pl.row_yy[2 * q + 1] = (unsigned char)y1;
+        }
+    if (unit_lds_bytes(pl.W, pl.N, pl.Cm, 2, false) > kLdsLimit ||
+        final_lds_bytes(pl.W, pl.H, pl.N, pl.Cm, pl.Rm, pl.Km) > kLdsLimit - 8 * 1024 ||
+        (size_t)7 * 8 * pl.R2 > kLdsLimit)
+        return TRS_ENOTIMPL;
+    // windows: distinct RS areas a with N a <= A_total < k N a (all areas when k = 0: one window)
+    std::vector<long long> areas;
+    for (int x0 = 0; x0 < pl.W; x0++)
+        for (int x1 = x0 + 1; x1 <= pl.W; x1++)
+            for (int y0 = 0; y0 < pl.H; y0++)
+                for (int y1 = y0 + 1; y1 <= pl.H; y1++)
+                    areas.push_back((long long)(pl.colpx[x1] - pl.colpx[x0]) * (pl.rowpx[y1] - pl.rowpx[y0]));
+    std::sort(areas.begin(), areas.end());
+    areas.erase(std::unique(areas.begin(), areas.end()), areas.end());
+    const long long At = (long long)pl.colpx[pl.W] * pl.rowpx[pl.H], N = pl.N;
+    pl.win.clear();
+    if (pl.karea == 0) pl.win.push_back(0);
+    else
+        for (long long a : areas)
+            if (N * a <= At && (long long)pl.karea * N * a > At) pl.win.push_back(a);
+    pl.n_win = (long long)pl.win.size();
+    // row boundaries: r = 1 .. Rm, each Y increasing from 0 to H, lexicographic
+    pl.yrow = pl.Rm + 2;
+    pl.ytab.clear();
+    std::vector<int> Y(pl.Rm + 1);
+    for (int r = 1; r <= pl.Rm; r++) {
+        for (int j = 0; j < r; j++) Y[j] = j;
+        Y[r] = pl.H;
+        while (true) {
+            pl.ytab.push_back((unsigned char)r);
+            for (int j = 0; j <= r; j++) pl.ytab.push_back((unsigned char)Y[j]);
+            for (int j = r + 1; j <= pl.Rm; j++) pl.ytab.push_back(0);
+            if ((long long)pl.ytab.size() / pl.yrow * std::max<long long>(pl.n_win, 1) > kUnitCap)
+                return TRS_ENOSPACE;
+            int j = r - 1;
+            while (j >= 1 && Y[j] >= pl.H - (r - j)) j--;
+            if (j < 1) break;
+            Y[j]++;
+            for (int q = j + 1; q < r; q++) Y[q] = Y[q - 1] + 1;
+        }
+    }
+    pl.nY = (long long)pl.ytab.size() / pl.yrow;
+    pl.n_units = pl.n_win * pl.nY;
+    if (pl.n_units > kUnitCap) return TRS_ENOSPACE;
+    trs_search_params lp = *p;
+    int32_t dt, dr;
+    int64_t n = 0;
+    trs_status st = space_size(pl.W, pl.H, &lp, &n, &dt, &dr);
+    if (st != TRS_OK) return st;
+    pl.n_enumerated = n;
+    return TRS_OK;
+}
+
+WsLayout layout(const LitPlan &pl)
+{
+    WsLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off += (bytes + 255) & ~size_t(255); return at; };
+    const size_t nrect = (size_t)pl.S * pl.R2, ntab = (size_t)pl.n_win * nrect * pl.Km;
+    L.hdr = take(256);
+    L.sat = take(3 * 8 * (size_t)(pl.W + 1) * (pl.H + 1));
+    L.rA = take(8 * nrect);
+    L.rT = take(8 * nrect);
+    L.rQ = take(8 * nrect);
+    L.tT = take(8 * ntab);
+    L.tQ = take(8 * ntab);
+    L.uQ = take(8 * (size_t)pl.n_units);
+    L.uT = take(8 * (size_t)pl.n_units);
+    L.uC = take(4 * (size_t)pl.n_units);
+    L.bytes = off;
+    return L;
+}
+
+std::vector<long long> key_of(const trs_frame *f, const trs_search_params *p)
+{
+    return {f->width, f->height, f->ctu_size, p->n_threads, p->max_tile_cols, p->max_tile_rows,
+            p->max_rs_per_tile, p->area_k};
+}
+
+// Plan for (f, p); caller holds g_mu.
+trs_status plan_for(const trs_frame *f, const trs_search_params *p, LitPlan **out)
+{
+    const auto key = key_of(f, p);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) {
+        LitPlan pl;
+        trs_status st = build(f, p, pl);
+        if (st != TRS_OK) return st;
+        it = g_plans.emplace(key, std::move(pl)).first;
+    }
+    *out = &it->second;
+    return TRS_OK;
+}
+
+template <class T>
+size_t put(std::vector<char> &blob, const std::vector<T> &v)
+{
+    const size_t at = (blob.size() + 15) & ~size_t(15);
+    blob.resize(at + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(blob.data() + at, v.data(), v.size() * sizeof(T));
+    return at;
+}
+
+trs_status view_of(LitPlan &pl, const trs_search_params *p, LitView *v)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TRS_EDEVICE;
+    if (pl.blob.empty()) {
+        pl.o_col = put(pl.blob, pl.colpx);
+        pl.o_row = put(pl.blob, pl.rowpx);
+        pl.o_win = put(pl.blob, pl.win);
+        pl.o_y = put(pl.blob, pl.ytab);
+        pl.o_sx = put(pl.blob, pl.strip_xy);
+        pl.o_ry = put(pl.blob, pl.row_yy);
+    }
+    auto it = pl.dev.find(dev);
+    if (it == pl.dev.end()) {
+        void *d = nullptr;
+        if (hipMalloc(&d, std::max<size_t>(pl.blob.size(), 16)) != hipSuccess) return TRS_EDEVICE;
+        if (hipMemcpy(d, pl.blob.data(), pl.blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return TRS_EDEVICE;
+        }
+        it = pl.dev.emplace(dev, d).first;
+    }
+    const char *d = static_cast<const char *>(it->second);
+    *v = LitView{};
+    v->W = pl.W; v->H = pl.H; v->N = pl.N; v->Cm = pl.Cm; v->Rm = pl.Rm; v->Km = pl.Km;
+    v->S = pl.S; v->R2 = pl.R2; v->n_win = (int)pl.n_win; v->nY = (int)pl.nY;
+    v->n_units = (int)pl.n_units; v->karea = pl.karea; v->yrow = pl.yrow;
+    v->lam_num = p->lambda_num < 0 ? -1 : p->lambda_num;
+    v->lam_den = p->lambda_den;
+    v->n_enumerated = pl.n_enumerated;
+    v->colpx = reinterpret_cast<const int *>(d + pl.o_col);
+    v->rowpx = reinterpret_cast<const int *>(d + pl.o_row);
+    v->win = reinterpret_cast<const long long *>(d + pl.o_win);
+    v->ytab = reinterpret_cast<const unsigned char *>(d + pl.o_y);
+    v->strip_xy = reinterpret_cast<const unsigned char *>(d + pl.o_sx);
+    v->row_yy = reinterpret_cast<const unsigned char *>(d + pl.o_ry);
+    return TRS_OK;
+}
+
+}  // namespace
+
+void release_all()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_plans)
+        for (auto &d : kv.second.dev) (void)hipFree(d.second);
+    g_plans.clear();
+}
+
+}  // namespace lit
+}  // namespace trs
+
+extern "C" trs_status trs_literal_workspace(const trs_frame *frame, const trs_search_params *params,
+                                            size_t *bytes)
+{
+    using namespace trs::lit;
+    if (!bytes) return TRS_EINVAL;
+    trs_status st = check_args(frame, params);
+    if (st != TRS_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    LitPlan *pl = nullptr;
+    st = plan_for(frame, params, &pl);
+    if (st != TRS_OK) return st;
+    *bytes = layout(*pl).bytes;
+    return TRS_OK;
+}
+
+extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_search_params *params,
+                                         const uint32_t *cost, const uint32_t *s1, const uint64_t *s2,
+                                         void *workspace, size_t ws_bytes, trs_result *out_dev,
+                                         hipStream_t stream)
+{
+    using namespace trs::lit;
+    trs_status st = check_args(frame, params);
+    if (st != TRS_OK) return st;
+    if (!cost || !s1 || !s2 || !out_dev) return TRS_EINVAL;
+    LitView v{};
+    WsLayout L{};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        LitPlan *pl = nullptr;
+        st = plan_for(frame, params, &pl);
+        if (st != TRS_OK) return st;
+        st = view_of(*pl, params, &v);
+        if (st != TRS_OK) return st;
+        L = layout(*pl);
+    }
+    if (!workspace || ws_bytes < L.bytes || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return TRS_EWORKSPACE;
+    char *ws = static_cast<char *>(workspace);
+    LitWs w{};
+    w.hdr = reinterpret_cast<unsigned long long *>(ws + L.hdr);
+    w.sat = reinterpret_cast<long long *>(ws + L.sat);
+    w.rA = reinterpret_cast<long long *>(ws + L.rA);
+    w.rT = reinterpret_cast<long long *>(ws + L.rT);
+    w.rQ = reinterpret_cast<long long *>(ws + L.rQ);
+    w.tT = reinterpret_cast<long long *>(ws + L.tT);
+    w.tQ = reinterpret_cast<long long *>(ws + L.tQ);
+    w.uQ = reinterpret_cast<long long *>(ws + L.uQ);
+    w.uT = reinterpret_cast<long long *>(ws + L.uT);
+    w.uC = reinterpret_cast<int *>(ws + L.uC);
+    const int nrect = v.S * v.R2;
+    hipLaunchKernelGGL(k_lit_sat, dim3(1), dim3(256), 0, stream, v, w, cost, s1, s2);
+    hipLaunchKernelGGL(k_lit_rects, dim3((nrect + 255) / 256), dim3(256), 0, stream, v, w);
+    if (v.n_units > 0) {
+        const size_t tl = (size_t)7 * 8 * v.R2;
+        const dim3 gt((unsigned)(v.n_win * v.S)), gu((unsigned)v.n_units);
+        hipLaunchKernelGGL(k_lit_tiles<1>, gt, dim3(256), tl, stream, v, w);
+        hipLaunchKernelGGL(k_lit_units<1>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, 1, false), stream, v, w);
+        hipLaunchKernelGGL(k_lit_tiles<2>, gt, dim3(256), tl, stream, v, w);
+        hipLaunchKernelGGL(k_lit_units<2>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, 2, false), stream, v, w);
+        hipLaunchKernelGGL(k_lit_pick, dim3(1), dim3(1024), 0, stream, v, w);
+    }
+    hipLaunchKernelGGL(k_lit_final, dim3(1), dim3(64), final_lds_bytes(v.W, v.H, v.N, v.Cm, v.Rm, v.Km),
+                       stream, v, w, out_dev);
+    return hipGetLastError() == hipSuccess ? TRS_OK : TRS_EDEVICE;
+}

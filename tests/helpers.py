@@ -59,6 +59,19 @@ def gpu_search(frame, params, cost: np.ndarray, s1: np.ndarray, s2: np.ndarray) 
     return B.read_result(out)
 
 
+def gpu_literal(frame, params, cost: np.ndarray, s1: np.ndarray, s2: np.ndarray) -> dict:
+    """The exact literal-space search on the GPU for one frame (host arrays in, result out)."""
+    import torch
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt)).cuda()
+    c = dev(np.asarray(cost, np.uint32), np.int32)
+    a = dev(np.asarray(s1, np.uint32), np.int32)
+    b = dev(np.asarray(s2, np.uint64), np.int64)
+    ws = torch.empty(B.trs_literal_workspace(frame, params), dtype=torch.uint8, device="cuda")
+    out = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    B.trs_literal_search(frame, params, c, a, b, ws, out)
+    return B.read_result(out)
+
+
 def oracle_params(orc, p: "B.SearchParams"):
     return orc.make_params(p.n_threads, p.max_tile_cols, p.max_tile_rows, p.max_rs_per_tile,
                            p.area_k, (p.lambda_num, p.lambda_den), p.dtile, p.drs, p.space_budget, p.prune,

@@ -209,3 +209,16 @@ def test_workload_lambdas_follow_the_policy():
     for (size, n), lam in synth.LAMBDA.items():
         w, h = synth.SIZES[size]
         assert Fraction(*B.trs_lambda_policy(B.make_frame(w, h), n)) == Fraction(*lam), (size, n)
+
+
+def test_literal_search_rejects_what_it_does_not_cover(lib):
+    fr = B.make_frame(1920, 1080)
+    cases = [(dict(dtile=3, drs=1), B.TRS_EINVAL), (dict(dtile=-1, drs=-1, prune=1), B.TRS_ENOTIMPL),
+             (dict(dtile=-1, drs=-1, min_rs=2), B.TRS_ENOTIMPL)]
+    for kw, status in cases:
+        with pytest.raises(B.TrsError) as e:
+            B.trs_literal_workspace(fr, B.make_params(4, 3, 3, 2, **kw))
+        assert e.value.status == status
+    with pytest.raises(B.TrsError) as e:
+        B.trs_literal_workspace(B.make_frame(7680, 4320), B.make_params(16, 8, 6, 4, dtile=-1, drs=-1))
+    assert e.value.status == B.TRS_ENOTIMPL
