@@ -59,9 +59,10 @@ def main():
     ap.add_argument("--sched-block", type=int, default=0)
     ap.add_argument("--sched-item", type=int, default=0)
     ap.add_argument("--streams", type=int, default=8, help="frames in flight (one stream each)")
-    ap.add_argument("--workload", default="uhd_seq", choices=["uhd_seq", "batch512", "mlp"],
+    ap.add_argument("--workload", default="uhd_seq", choices=["uhd_seq", "batch512", "mlp", "literal"],
                     help="uhd_seq: the 64-frame 4K sequence; batch512: 512 mixed frames in one batch; "
-                         "mlp: training steps of the learned CTU-time predictor")
+                         "mlp: training steps of the learned CTU-time predictor; literal: exact search "
+                         "of 4K frames over the literal space (every CTU boundary allowed)")
     ap.add_argument("--mlp-batch", type=int, default=65536)
     ap.add_argument("--prune", type=int, default=0,
                     help="optional pruning rules (bit 0: slice heights, bit 1: mean areas); 0 = the paper's method")
@@ -79,6 +80,8 @@ def main():
         return run_batch(args)
     if args.workload == "mlp":
         return run_mlp(args)
+    if args.workload == "literal":
+        return run_literal(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build partitions frames on a single MI355X "
@@ -709,6 +712,147 @@ def run_mlp(args):
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# DP relaxations of the literal-space search and the lane-ops charged to each: a step-1
+# relaxation is a 64-bit max and a 64-bit compare-select (6 lane-ops), a step-2 relaxation adds
+# a 64-bit sum and compares (Q, T~) lexicographically (10 lane-ops).
+LIT_OPS = {1: 6, 2: 10}
+
+
+def literal_relaxations(w, h, N, Cm, Rm, Km, area_k=3, cs=128):
+    """(tile-table relaxations, unit relaxations) of one step of the literal search, counted
+    from the loop bounds of the three DPs: split rows per (window, strip, row pair, k), and per
+    (window, row boundaries) the strip DP over tiles and the column DP over (columns, RS)."""
+    from math import comb
+    W, H = (w + cs - 1) // cs, (h + cs - 1) // cs
+    Cm, Rm, Km = min(Cm, W), min(Rm, H), min(Km, H)
+    cw = [min(cs, w - x * cs) for x in range(W)]
+    rh = [min(cs, h - y * cs) for y in range(H)]
+    widths = {sum(cw[a:b]) for a in range(W) for b in range(a + 1, W + 1)}
+    heights = {sum(rh[a:b]) for a in range(H) for b in range(a + 1, H + 1)}
+    areas = {x * y for x in widths for y in heights}
+    n_win = 1 if area_k == 0 else sum(1 for a in areas if N * a <= w * h < area_k * N * a)
+    S = W * (W + 1) // 2
+    per_strip = sum(max(0, (y - y0) - q + 1) if q > 1 else 1
+                    for y0 in range(H) for y in range(y0 + 1, H + 1) for q in range(1, Km + 1))
+    tiles = n_win * S * per_strip
+    knap = sum(min(Km, K) for K in range(N + 1))
+    colB = sum((x - i + 1) * n for x in range(1, W + 1) for i in range(1, min(x, Cm) + 1)
+               for n in range(1, N + 1))
+    units = 0
+    for r in range(1, Rm + 1):
+        nY = comb(H - 1, r - 1)
+        colA = sum(x * r * knap for x in range(1, W + 1))
+        units += n_win * nY * (colA + colB)
+    return tiles, units
+
+
+def run_literal(args):
+    """4K frames searched exactly over the literal space (5.4e9 candidates per frame): per
+    frame the feature kernel, the time map and trs_literal_search, frames one after another
+    on one stream with one workspace."""
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2012_14792_amd import binding as B
+    from paper_2012_14792_amd import synth
+
+    torch.cuda.set_device(0)
+    w, h, N, C, R, K, lam = 3840, 2160, 8, 6, 4, 4, (1, 10)
+    F = 8 if args.frames == 64 else args.frames
+    frame = B.make_frame(w, h)
+    W, H = B.ctu_dims(frame)
+    params = B.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1)
+    gen = synth.SequenceGenerator(w, h, 2, 8.0)
+    lum_np = [gen.frame(f) for f in range(F + 1)]
+    luma = [torch.from_numpy(x.view(np.int16)).cuda() for x in lum_np]
+    feats = [B.alloc_features(frame) for _ in range(F + 1)]
+    for f in range(F + 1):
+        B.trs_features(frame, luma[f], feats[f])
+    eps = synth.ar1_eps(W * H, F + 1, 2000)
+    truth = [synth.ctu_times(feats[f]["tex"].cpu().numpy().view(np.uint32), eps[f]) for f in range(F + 1)]
+    prev = [torch.from_numpy(truth[f].view(np.int32)).cuda() for f in range(F + 1)]
+    cost = [torch.empty(W * H, dtype=torch.int32, device="cuda") for _ in range(F + 1)]
+    ws = torch.empty(B.trs_literal_workspace(frame, params), dtype=torch.uint8, device="cuda")
+    out = torch.empty((F + 1, B.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+    blend = B.Blend(200, 3, 256)
+    n_space = B.trs_space_size(frame, params)[0]
+
+    def step():
+        for f in range(1, F + 1):
+            B.trs_features(frame, luma[f], feats[f])
+            B.trs_cost_map(frame, feats[f]["tex"], prev[f - 1], blend, cost[f])
+            B.trs_literal_search(frame, params, cost[f], feats[f]["s1"], feats[f]["s2"], ws, out[f])
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fps = F * args.steps / el
+    log(f"literal search: {fps:.1f} 4K frames/s ({el / args.steps / F * 1e3:.3f} ms per frame)")
+
+    # stage durations with events on the launching stream, one eager pass
+    B.trs_profile_enable(1)
+    step()
+    torch.cuda.synchronize()
+    B.trs_profile_enable(0)
+    st, runs = B.trs_profile_read_literal()
+    st = {k: v / runs for k, v in st.items()}
+    tiles, units = literal_relaxations(w, h, N, C, R, K)
+    ops = {"tiles1": tiles * LIT_OPS[1], "units1": units * LIT_OPS[1], "tiles2": tiles * LIT_OPS[2],
+           "units2": units * LIT_OPS[2]}
+    dom = max(ops, key=lambda k: st[k])
+    ach = ops[dom] / (st[dom] * 1e-3) / 1e12
+    res = [B.read_result(out[f]) for f in range(1, F + 1)]
+    log("stages (ms per frame): " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
+
+    cpu, parity = None, "not checked (--no-cpu-baseline)"
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        f = 1
+        fo = orc.features(lum_np[f])
+        c_np, _ = orc.cost_map(fo["tex"], truth[f - 1])
+        t1 = time.perf_counter()
+        ref = orc.literal_search(w, h, orc.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1), c_np,
+                                 fo["s1"], fo["s2"])
+        wall = time.perf_counter() - t1
+        keys = ("status", "t_min", "t_sel", "q_sel", "n_enumerated", "tile_cols", "tile_rows",
+                "col_bd", "row_bd", "rs", "rs_time", "t_unif", "q_unif")
+        same = all(res[f - 1][k] == ref[k] for k in keys)
+        parity = f"frame {f} bit-exact vs oracle: {same}"
+        cpu = {"value": round(1.0 / wall, 4), "unit": "4K frames/s", "cores": 1, "kind": "oracle",
+               "sample": f"frame {f}: oracle literal-space search by the same decomposition in plain C, "
+                         f"one thread, {wall:.1f} s"}
+        log(f"cpu baseline: {wall:.1f} s per frame; {parity}")
+
+    out_j = {
+        "metric": "4K frames/s, exact search over the literal space (every CTU boundary allowed)",
+        "value": round(fps, 2), "unit": "4K frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"{F} frames of the 3840x2160 drifting sequence (seed 2), N=8, tiles <= 6x4, "
+                               f"<= 4 RS per tile, lambda 1/10, literal space ({n_space} candidates/frame)",
+                   "frames_per_step": F},
+        "stage_ms_per_frame": {k: round(v, 4) for k, v in st.items()},
+        "relaxations_per_frame": {"tiles (each step)": tiles, "units (each step)": units},
+        "roofline": {"bound": "alu", "kernel": {"units1": "k_lit_units<1>", "units2": "k_lit_units<2>",
+                                                "tiles1": "k_lit_tiles<1>", "tiles2": "k_lit_tiles<2>"}[dom],
+                     "achieved": round(ach, 3), "peak": PEAK_ALU_TOPS, "unit": "T lane-ops/s",
+                     "frac": round(ach / PEAK_ALU_TOPS, 4), "traffic": None},
+        "t_min_frames": [r["t_min"] for r in res],
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out_j), flush=True)
 
 
 if __name__ == "__main__":

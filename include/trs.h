@@ -203,6 +203,13 @@ trs_status trs_literal_search(const trs_frame *frame, const trs_search_params *p
                               void *workspace, size_t ws_bytes, trs_result *out_dev,
                               hipStream_t stream);
 
+/* Per-stage durations (ms, summed) of the trs_literal_search calls made while profiling was
+ * on (trs_profile_enable), then forgets them: ms[0] prefix sums and rectangle values, ms[1]
+ * step-1 tile tables, ms[2] step-1 units, ms[3] step-2 tile tables, ms[4] step-2 units,
+ * ms[5] unit reduction, ms[6] rebuild and result; *runs = number of searches.  Waits for the
+ * last recorded event.  Errors: TRS_EINVAL, TRS_EDEVICE. */
+trs_status trs_profile_read_literal(double *ms, int64_t *runs);
+
 /* The whole per-frame path in one call (Fig. 3 of the paper: current-frame luma and the
  * co-located previous times in, partition out): trs_features, trs_cost_map and trs_search
  * enqueued on one stream, with the cost map fused into the prefix-sum kernel when the CTU

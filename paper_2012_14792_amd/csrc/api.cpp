@@ -19,6 +19,7 @@
 namespace trs {
 namespace lit {
 void release_all();   // literal-space plans (literal.hip)
+void profile_enable(bool on);
 }
 }  // namespace trs
 
@@ -380,6 +381,7 @@ trs_status trs_partition(const trs_frame *frame, const trs_search_params *params
 
 void trs_profile_enable(int on)
 {
+    trs::lit::profile_enable(on != 0);
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
 }

@@ -26,7 +26,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -55,10 +57,12 @@ struct LitView {
     const unsigned char *ytab;          // per Y: r, then Y_0 .. Y_r (yrow bytes per entry)
     const unsigned char *strip_xy;      // per strip: x0, x1
     const unsigned char *row_yy;        // per row pair: y0, y1
+    const int *worder;                  // windows in dispatch order (likeliest to win first)
 };
 
 struct LitWs {
-    unsigned long long *hdr;            // [0] T~min, [1] winning unit, [2] its column count
+    unsigned long long *hdr;            // [0] T~min, [1] winning unit, [2] its column count,
+                                        // [3] least Q of a unit so far (step-2 pruning bound)
     long long *sat;                     // 3 inclusive prefix sums, (H + 1) x (W + 1) each
     long long *rA, *rT, *rQ;            // per rectangle [S][R2]: area, time, q
     long long *tT, *tQ;                 // per [window][strip][row pair][k - 1]
@@ -101,6 +105,7 @@ k_lit_sat(LitView v, LitWs w, const uint32_t *__restrict__ cost, const uint32_t 
         w.hdr[0] = kNone;
         w.hdr[1] = kNone;
         w.hdr[2] = 0;
+        w.hdr[3] = kNone;
     }
     // rows: running sums along x
     for (int t = threadIdx.x; t < 3 * (H + 1); t += blockDim.x) {
@@ -211,16 +216,25 @@ k_lit_tiles(LitView v, LitWs w)
 
 // ---------------------------------------------------------------------------------------
 // The column DP of one unit (window, Y) by one wave.  LDS: strip values hs[x'][K] for the
-// strips ending at the current x, the DP table F[i][x][n], and with REC the argmins.
+// strips ending at the current x, the DP table F[i][x][n], a flag per hs row and per (i, x) row
+// telling whether it holds a finite value, and with REC the argmins.
+//
+// Pruning (exact): a state whose T~ exceeds bt, or whose Q exceeds bq, becomes infinite.  Step
+// 1 passes the Eq. 4 bound of the best T~min found so far (or that T~min when lambda is
+// infinite), so every unit whose own minimum is within the final bound still reports it exactly;
+// step 2 passes the best Q found so far (Q of a partial partition only grows, as every RS has
+// q >= 0).  A partition through a pruned state cannot be the optimum.  REC (the rebuild) prunes
+// nothing, so its argmins are those of the full DP.
 struct UnitLds {
     long long *hsT, *hsQ, *FT, *FQ;
+    unsigned *hsOk, *FOk;
     unsigned char *AX, *AK;
 };
 
 __host__ __device__ inline size_t unit_lds_bytes(int W, int N, int Cm, int step, bool rec)
 {
     const size_t hs = (size_t)W * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
-    size_t b = 8 * (hs + F) * (step == 2 ? 2 : 1);
+    size_t b = 8 * (hs + F) * (step == 2 ? 2 : 1) + 4 * ((size_t)W + (size_t)(Cm + 1) * (W + 1));
     if (rec) b += 2 * F;
     return (b + 15) & ~size_t(15);
 }
@@ -234,13 +248,17 @@ __device__ inline UnitLds unit_lds(unsigned char *raw, int W, int N, int Cm, int
     if (step == 2) { L.hsQ = p; p += hs; }
     L.FT = p; p += F;
     if (step == 2) { L.FQ = p; p += F; }
-    unsigned char *c = reinterpret_cast<unsigned char *>(p);
+    unsigned *o = reinterpret_cast<unsigned *>(p);
+    L.hsOk = o; o += W;
+    L.FOk = o; o += (size_t)(Cm + 1) * (W + 1);
+    unsigned char *c = reinterpret_cast<unsigned char *>(o);
     if (rec) { L.AX = c; L.AK = c + F; }
     return L;
 }
 
 template <int STEP, bool REC>
-__device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &L, int *Yl, int &r)
+__device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &L, int *Yl, int &r,
+                        long long bt, long long bq)
 {
     const int lane = threadIdx.x;
     const int W = v.W, N = v.N, Cm = v.Cm, Km = v.Km, S = v.S, R2 = v.R2;
@@ -253,12 +271,14 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
         L.FT[e] = kInf;
         if (STEP == 2) L.FQ[e] = kInf;
     }
+    for (int e = lane; e < (Cm + 1) * (W + 1); e += blockDim.x) L.FOk[e] = e == 0;
     __syncthreads();
     if (lane == 0) {
         L.FT[0] = 0;
         if (STEP == 2) L.FQ[0] = 0;
     }
     auto fi = [&](int i, int x, int n) { return ((size_t)i * (W + 1) + x) * (N + 1) + n; };
+    auto keep = [&](long long t, long long q) { return t <= bt && (STEP == 1 || q <= bq); };
     for (int x = 1; x <= W; x++) {
         // strips [x', x): DP over the r tiles, in place in row x' of hs
         for (int xp = lane; xp < x; xp += blockDim.x) {
@@ -269,44 +289,54 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
                 if (STEP == 2) hQ[K] = K == 0 ? 0 : kInf;
             }
             const size_t sb = (size_t)wi * S + sidx(xp, x, W);
-            for (int j = 0; j < r; j++) {
+            bool any = true;
+            for (int j = 0; j < r && any; j++) {
                 const size_t tb = (sb * R2 + ridx(Yl[j], Yl[j + 1], v.H)) * Km;
+                any = false;
                 for (int K = N; K >= 0; K--) {
-                    long long bt = kInf, bq = kInf;
+                    long long ct = kInf, cq = kInf;
                     for (int k = 1; k <= Km && k <= K; k++) {
-                        const long long at = hT[K - k], ct = w.tT[tb + k - 1];
-                        if (at == kInf || ct == kInf) continue;
-                        const long long t = at > ct ? at : ct;
+                        const long long at = hT[K - k], tt = w.tT[tb + k - 1];
+                        if (at == kInf || tt == kInf) continue;
+                        const long long t = at > tt ? at : tt;
                         const long long q = STEP == 2 ? hQ[K - k] + w.tQ[tb + k - 1] : 0;
-                        if (better<STEP>(q, t, bq, bt)) { bt = t; bq = q; }
+                        if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; }
                     }
-                    hT[K] = bt;
-                    if (STEP == 2) hQ[K] = bq;
+                    if (ct != kInf && !REC && !keep(ct, cq)) ct = cq = kInf;
+                    hT[K] = ct;
+                    if (STEP == 2) hQ[K] = cq;
+                    any |= ct != kInf;
                 }
             }
+            if (!any)
+                for (int K = 0; K <= N; K++) hT[K] = kInf;
+            L.hsOk[xp] = any;
         }
         __syncthreads();
         // states (i, n) at x
         for (int st = lane; st < Cm * N; st += blockDim.x) {
             const int i = 1 + st / N, n = 1 + st % N;
             if (i > x) continue;
-            long long bt = kInf, bq = kInf;
+            long long ct = kInf, cq = kInf;
             int ax = -1, ak = -1;
             for (int xp = i - 1; xp < x; xp++) {
+                if (!L.hsOk[xp] || !L.FOk[(i - 1) * (W + 1) + xp]) continue;
                 const long long *hT = L.hsT + (size_t)xp * (N + 1);
                 for (int K = 1; K <= n; K++) {
                     const size_t fp = fi(i - 1, xp, n - K);
-                    const long long at = L.FT[fp], ct = hT[K];
-                    if (at == kInf || ct == kInf) continue;
-                    const long long t = at > ct ? at : ct;
+                    const long long at = L.FT[fp], tt = hT[K];
+                    if (at == kInf || tt == kInf) continue;
+                    const long long t = at > tt ? at : tt;
                     const long long q = STEP == 2 ? L.FQ[fp] + L.hsQ[(size_t)xp * (N + 1) + K] : 0;
-                    if (better<STEP>(q, t, bq, bt)) { bt = t; bq = q; ax = xp; ak = K; }
+                    if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; ax = xp; ak = K; }
                 }
             }
+            if (ct != kInf && !REC && !keep(ct, cq)) ct = cq = kInf;
             const size_t f = fi(i, x, n);
-            L.FT[f] = bt;
-            if (STEP == 2) L.FQ[f] = bq;
+            L.FT[f] = ct;
+            if (STEP == 2) L.FQ[f] = cq;
             if (REC) { L.AX[f] = (unsigned char)ax; L.AK[f] = (unsigned char)ak; }
+            if (ct != kInf) L.FOk[i * (W + 1) + x] = 1;
         }
         __syncthreads();
     }
@@ -318,25 +348,41 @@ k_lit_units(LitView v, LitWs w)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int Yl[kMaxH + 1];
-    const int u = blockIdx.x;
-    if (STEP == 2 && w.hdr[0] == kNone) return;
+    const int u = v.worder[blockIdx.x / v.nY] * v.nY + (int)(blockIdx.x % v.nY);
+    long long bt = kInf, bq = kInf;
+    if (STEP == 1) {
+        const unsigned long long best = __atomic_load_n(&w.hdr[0], __ATOMIC_RELAXED);
+        if (best != kNone) bt = v.lam_num < 0 ? (long long)best : (long long)eq4_bound(best, v.lam_num, v.lam_den);
+    } else {
+        const unsigned long long tmin = w.hdr[0];
+        if (tmin == kNone) return;
+        const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
+        if (v.lam_num >= 0 && (unsigned long long)w.uT[u] > tau) {       // no candidate within Eq. 4
+            if (threadIdx.x == 0) { w.uQ[u] = kInf; w.uT[u] = kInf; w.uC[u] = 0; }
+            return;
+        }
+        const unsigned long long qb = __atomic_load_n(&w.hdr[3], __ATOMIC_RELAXED);
+        if (qb != kNone) bq = (long long)qb;
+    }
     const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, STEP, false);
     int r = 0;
-    unit_dp<STEP, false>(v, w, u, L, Yl, r);
+    unit_dp<STEP, false>(v, w, u, L, Yl, r, bt, bq);
     if (threadIdx.x != 0) return;
-    long long bt = kInf, bq = kInf;
+    long long ct = kInf, cq = kInf;
     int bc = 0;
     for (int c = 1; c <= v.Cm; c++) {
         const size_t f = ((size_t)c * (v.W + 1) + v.W) * (v.N + 1) + v.N;
         const long long t = L.FT[f], q = STEP == 2 ? L.FQ[f] : 0;
-        if (t != kInf && better<STEP>(q, t, bq, bt)) { bt = t; bq = q; bc = c; }
+        if (t != kInf && better<STEP>(q, t, cq, ct)) { ct = t; cq = q; bc = c; }
     }
     if (STEP == 1) {
-        if (bt != kInf) atomicMin(w.hdr, (unsigned long long)bt);
+        w.uT[u] = ct;                                   // the unit's own minimum (kInf if pruned)
+        if (ct != kInf) atomicMin(w.hdr, (unsigned long long)ct);
     } else {
-        w.uQ[u] = bq;
-        w.uT[u] = bt;
+        w.uQ[u] = cq;
+        w.uT[u] = ct;
         w.uC[u] = bc;
+        if (ct != kInf) atomicMin(w.hdr + 3, (unsigned long long)cq);
     }
 }
 
@@ -412,7 +458,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
     const unsigned long long tmin = w.hdr[0];
     const bool feasible = tmin != kNone && w.hdr[1] != kNone;
     int r = 0;
-    if (feasible) unit_dp<2, true>(v, w, (int)w.hdr[1], L, Yl, r);
+    if (feasible) unit_dp<2, true>(v, w, (int)w.hdr[1], L, Yl, r, kInf, kInf);
     if (lane == 0) {
         auto rect_at = [&](const long long *a, int x0, int x1, int y0, int y1) {
             return a[(size_t)sidx(x0, x1, W) * v.R2 + ridx(y0, y1, H)];
@@ -573,9 +619,10 @@ struct LitPlan {
     long long n_win = 0, nY = 0, n_units = 0, n_enumerated = 0;
     std::vector<int> colpx, rowpx;
     std::vector<long long> win;
+    std::vector<int> worder;
     std::vector<unsigned char> ytab, strip_xy, row_yy;
     std::vector<char> blob;             // the tables above, packed for the device copy
-    size_t o_col = 0, o_row = 0, o_win = 0, o_y = 0, o_sx = 0, o_ry = 0;
+    size_t o_col = 0, o_row = 0, o_win = 0, o_y = 0, o_sx = 0, o_ry = 0, o_wo = 0;
     std::map<int, void *> dev;          // device copies of the tables
 };
 
@@ -585,6 +632,12 @@ struct WsLayout {
 
 std::mutex g_mu;
 std::map<std::vector<long long>, LitPlan> g_plans;
+
+// Stage timing while profiling is on: events around the launches of every search.
+constexpr int kStages = 7;     // prefix sums + rectangles, tiles 1, units 1, tiles 2, units 2, pick, final
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::array<hipEvent_t, kStages + 1>> g_prof_ev;
 
 trs_status check_args(const trs_frame *f, const trs_search_params *p)
 {
@@ -647,6 +700,16 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
         for (long long a : areas)
             if (N * a <= At && (long long)pl.karea * N * a > At) pl.win.push_back(a);
     pl.n_win = (long long)pl.win.size();
+    // Dispatch order of the windows (speed only: ties are broken by unit index): nearest first
+    // to 3/4 of the mean RS area, where the smallest area of a balanced partition tends to lie,
+    // so that the pruning bounds tighten early.
+    pl.worder.resize(pl.win.size());
+    for (size_t i = 0; i < pl.win.size(); i++) pl.worder[i] = (int)i;
+    {
+        const double target = 0.75 * (double)At / (double)N;
+        auto dist = [&](int i) { return std::fabs(std::log(std::max<double>((double)pl.win[i], 1.0) / target)); };
+        std::stable_sort(pl.worder.begin(), pl.worder.end(), [&](int a, int b) { return dist(a) < dist(b); });
+    }
     // row boundaries: r = 1 .. Rm, each Y increasing from 0 to H, lexicographic
     pl.yrow = pl.Rm + 2;
     pl.ytab.clear();
@@ -740,6 +803,7 @@ trs_status view_of(LitPlan &pl, const trs_search_params *p, LitView *v)
         pl.o_y = put(pl.blob, pl.ytab);
         pl.o_sx = put(pl.blob, pl.strip_xy);
         pl.o_ry = put(pl.blob, pl.row_yy);
+        pl.o_wo = put(pl.blob, pl.worder);
     }
     auto it = pl.dev.find(dev);
     if (it == pl.dev.end()) {
@@ -765,10 +829,17 @@ trs_status view_of(LitPlan &pl, const trs_search_params *p, LitView *v)
     v->ytab = reinterpret_cast<const unsigned char *>(d + pl.o_y);
     v->strip_xy = reinterpret_cast<const unsigned char *>(d + pl.o_sx);
     v->row_yy = reinterpret_cast<const unsigned char *>(d + pl.o_ry);
+    v->worder = reinterpret_cast<const int *>(d + pl.o_wo);
     return TRS_OK;
 }
 
 }  // namespace
+
+void profile_enable(bool on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on;
+}
 
 void release_all()
 {
@@ -830,19 +901,64 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
     w.uQ = reinterpret_cast<long long *>(ws + L.uQ);
     w.uT = reinterpret_cast<long long *>(ws + L.uT);
     w.uC = reinterpret_cast<int *>(ws + L.uC);
+    std::array<hipEvent_t, kStages + 1> ev{};
+    bool prof = false;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
+    if (prof)
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return TRS_EDEVICE;
+    auto mark = [&](int i) { if (prof) (void)hipEventRecord(ev[i], stream); };
     const int nrect = v.S * v.R2;
+    mark(0);
     hipLaunchKernelGGL(k_lit_sat, dim3(1), dim3(256), 0, stream, v, w, cost, s1, s2);
     hipLaunchKernelGGL(k_lit_rects, dim3((nrect + 255) / 256), dim3(256), 0, stream, v, w);
+    mark(1);
     if (v.n_units > 0) {
         const size_t tl = (size_t)7 * 8 * v.R2;
         const dim3 gt((unsigned)(v.n_win * v.S)), gu((unsigned)v.n_units);
         hipLaunchKernelGGL(k_lit_tiles<1>, gt, dim3(256), tl, stream, v, w);
+        mark(2);
         hipLaunchKernelGGL(k_lit_units<1>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, 1, false), stream, v, w);
+        mark(3);
         hipLaunchKernelGGL(k_lit_tiles<2>, gt, dim3(256), tl, stream, v, w);
+        mark(4);
         hipLaunchKernelGGL(k_lit_units<2>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, 2, false), stream, v, w);
+        mark(5);
         hipLaunchKernelGGL(k_lit_pick, dim3(1), dim3(1024), 0, stream, v, w);
+        mark(6);
+    } else {
+        for (int i = 2; i <= 6; i++) mark(i);
     }
     hipLaunchKernelGGL(k_lit_final, dim3(1), dim3(64), final_lds_bytes(v.W, v.H, v.N, v.Cm, v.Rm, v.Km),
                        stream, v, w, out_dev);
+    mark(7);
+    if (prof) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_ev.push_back(ev);
+    }
     return hipGetLastError() == hipSuccess ? TRS_OK : TRS_EDEVICE;
+}
+
+extern "C" trs_status trs_profile_read_literal(double *ms, int64_t *runs)
+{
+    using namespace trs::lit;
+    if (!ms || !runs) return TRS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int i = 0; i < kStages; i++) ms[i] = 0;
+    trs_status st = TRS_OK;
+    for (auto &ev : g_prof_ev) {
+        if (hipEventSynchronize(ev[kStages]) != hipSuccess) st = TRS_EDEVICE;
+        for (int i = 0; i < kStages && st == TRS_OK; i++) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = TRS_EDEVICE;
+            ms[i] += t;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    *runs = (int64_t)g_prof_ev.size();
+    g_prof_ev.clear();
+    return st;
 }
