@@ -62,7 +62,8 @@ struct LitView {
 
 struct LitWs {
     unsigned long long *hdr;            // [0] T~min, [1] winning unit, [2] its column count,
-                                        // [3] least Q of a unit so far (step-2 pruning bound)
+                                        // [3] least Q of a unit so far (step-2 pruning bound),
+                                        // [4] 1 when the frame's total time is below 2^32 - 1
     long long *sat;                     // 3 inclusive prefix sums, (H + 1) x (W + 1) each
     long long *rA, *rT, *rQ;            // per rectangle [S][R2]: area, time, q
     long long *tT, *tQ;                 // per [window][strip][row pair][k - 1]
@@ -86,6 +87,19 @@ __device__ __forceinline__ unsigned long long eq4_bound(unsigned long long tmin,
     return tmin * (unsigned long long)(den + num) / (unsigned long long)den;
 }
 
+// Quotient and remainder by a small divisor d (1 <= d <= 4096) for e < 2^16 without a divide:
+// m = ceil(2^16 / d) overshoots e / d by less than one, which one correction step removes.
+struct SmallDiv {
+    unsigned d, m;
+    __device__ explicit SmallDiv(unsigned dd) : d(dd), m((65536u + dd - 1) / dd) {}
+    __device__ __forceinline__ void divmod(unsigned e, unsigned &q, unsigned &rr) const
+    {
+        q = (e * m) >> 16;
+        if (q * d > e) q--;
+        rr = e - q * d;
+    }
+};
+
 // Step-2 values compare by Q, then T~; step 1 by T~ alone (q stays 0).
 template <int STEP>
 __device__ __forceinline__ bool better(long long aq, long long at, long long bq, long long bt)
@@ -106,6 +120,7 @@ k_lit_sat(LitView v, LitWs w, const uint32_t *__restrict__ cost, const uint32_t 
         w.hdr[1] = kNone;
         w.hdr[2] = 0;
         w.hdr[3] = kNone;
+        w.hdr[4] = 0;
     }
     // rows: running sums along x
     for (int t = threadIdx.x; t < 3 * (H + 1); t += blockDim.x) {
@@ -131,6 +146,7 @@ k_lit_sat(LitView v, LitWs w, const uint32_t *__restrict__ cost, const uint32_t 
             acc += base[(size_t)y * (W + 1)];
             base[(size_t)y * (W + 1)] = acc;
         }
+        if (a == 0 && x == W) w.hdr[4] = acc < 0xffffffffll;   // every time sum fits 32 bits
     }
 }
 
@@ -227,27 +243,33 @@ k_lit_tiles(LitView v, LitWs w)
 // nothing, so its argmins are those of the full DP.
 struct UnitLds {
     long long *hsT, *hsQ, *FT, *FQ;
+    long long *tvT, *tvQ;               // tile values of the strips ending at the current x
     unsigned *hsOk, *FOk;
     unsigned char *AX, *AK;
 };
 
-__host__ __device__ inline size_t unit_lds_bytes(int W, int N, int Cm, int step, bool rec)
+__host__ __device__ inline size_t unit_lds_bytes(int W, int N, int Cm, int Rm, int Km, int step, bool rec)
 {
     const size_t hs = (size_t)W * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
-    size_t b = 8 * (hs + F) * (step == 2 ? 2 : 1) + 4 * ((size_t)W + (size_t)(Cm + 1) * (W + 1));
+    const size_t tv = (size_t)W * Rm * Km;
+    size_t b = 8 * (hs + F + tv) * (step == 2 ? 2 : 1) + 4 * ((size_t)W + (size_t)(Cm + 1) * (W + 1));
     if (rec) b += 2 * F;
     return (b + 15) & ~size_t(15);
 }
 
-__device__ inline UnitLds unit_lds(unsigned char *raw, int W, int N, int Cm, int step, bool rec)
+__device__ inline UnitLds unit_lds(unsigned char *raw, int W, int N, int Cm, int Rm, int Km, int step,
+                                   bool rec)
 {
     const size_t hs = (size_t)W * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    const size_t tv = (size_t)W * Rm * Km;
     UnitLds L{};
     long long *p = reinterpret_cast<long long *>(raw);
     L.hsT = p; p += hs;
     if (step == 2) { L.hsQ = p; p += hs; }
     L.FT = p; p += F;
     if (step == 2) { L.FQ = p; p += F; }
+    L.tvT = p; p += tv;
+    if (step == 2) { L.tvQ = p; p += tv; }
     unsigned *o = reinterpret_cast<unsigned *>(p);
     L.hsOk = o; o += W;
     L.FOk = o; o += (size_t)(Cm + 1) * (W + 1);
@@ -279,7 +301,19 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
     }
     auto fi = [&](int i, int x, int n) { return ((size_t)i * (W + 1) + x) * (N + 1) + n; };
     auto keep = [&](long long t, long long q) { return t <= bt && (STEP == 1 || q <= bq); };
+    const int Rm = v.Rm;
     for (int x = 1; x <= W; x++) {
+        // tile values (k = 1 .. Km) of the r tiles of every strip [x', x), loaded together
+        for (int e = lane; e < x * r; e += blockDim.x) {
+            const int xp = e / r, j = e % r;
+            const size_t tb = (((size_t)wi * S + sidx(xp, x, W)) * R2 + ridx(Yl[j], Yl[j + 1], v.H)) * Km;
+            const size_t lb = ((size_t)xp * Rm + j) * Km;
+            for (int k = 0; k < Km; k++) {
+                L.tvT[lb + k] = w.tT[tb + k];
+                if (STEP == 2) L.tvQ[lb + k] = w.tQ[tb + k];
+            }
+        }
+        __syncthreads();
         // strips [x', x): DP over the r tiles, in place in row x' of hs
         for (int xp = lane; xp < x; xp += blockDim.x) {
             long long *hT = L.hsT + (size_t)xp * (N + 1);
@@ -288,18 +322,18 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
                 hT[K] = K == 0 ? 0 : kInf;
                 if (STEP == 2) hQ[K] = K == 0 ? 0 : kInf;
             }
-            const size_t sb = (size_t)wi * S + sidx(xp, x, W);
             bool any = true;
             for (int j = 0; j < r && any; j++) {
-                const size_t tb = (sb * R2 + ridx(Yl[j], Yl[j + 1], v.H)) * Km;
+                const long long *tvT = L.tvT + ((size_t)xp * Rm + j) * Km;
+                const long long *tvQ = STEP == 2 ? L.tvQ + ((size_t)xp * Rm + j) * Km : nullptr;
                 any = false;
                 for (int K = N; K >= 0; K--) {
                     long long ct = kInf, cq = kInf;
                     for (int k = 1; k <= Km && k <= K; k++) {
-                        const long long at = hT[K - k], tt = w.tT[tb + k - 1];
+                        const long long at = hT[K - k], tt = tvT[k - 1];
                         if (at == kInf || tt == kInf) continue;
                         const long long t = at > tt ? at : tt;
-                        const long long q = STEP == 2 ? hQ[K - k] + w.tQ[tb + k - 1] : 0;
+                        const long long q = STEP == 2 ? hQ[K - k] + tvQ[k - 1] : 0;
                         if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; }
                     }
                     if (ct != kInf && !REC && !keep(ct, cq)) ct = cq = kInf;
@@ -342,7 +376,120 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
     }
 }
 
-template <int STEP>
+// Step 1 without argmins, balanced over the lanes: the strip DP takes one (x', K) pair per lane
+// (rows of hs double-buffered per tile), the column DP one (i, x') pair per lane, each folding
+// its candidates for every n into F[i][x][n] with an LDS atomic minimum.  Same values as
+// unit_dp<1, false>: the minimum of a set does not depend on the order it is taken in.  V is the
+// value type: 32-bit when the frame's total predicted time is below 2^32 - 1 (every region sum
+// then fits), else 64-bit; its largest value is the "none" sentinel, which max() propagates and
+// min() ignores, so no separate test is needed.
+template <class V>
+__device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char *raw, int *Yl, int &r,
+                         long long bt_in, long long *result)
+{
+    constexpr V kNo = ~V(0);
+    // a value maps to the sentinel when it is infinite or does not fit below it
+    auto narrow = [&](long long t) {
+        return (t == kInf || (unsigned long long)t >= (unsigned long long)kNo) ? kNo : (V)t;
+    };
+    const V bt = bt_in == kInf ? V(kNo - 1) : (narrow(bt_in) == kNo ? V(kNo - 1) : (V)bt_in);
+    const int lane = threadIdx.x;
+    const int W = v.W, N = v.N, Cm = v.Cm, Km = v.Km, S = v.S, R2 = v.R2, Rm = v.Rm, NP = N + 1;
+    const int wi = u / v.nY, yi = u % v.nY;
+    const size_t F = (size_t)(Cm + 1) * (W + 1) * NP;
+    V *FT = reinterpret_cast<V *>(raw);
+    V *hsA = FT + F, *hsB = hsA + (size_t)W * NP;
+    V *tv = hsB + (size_t)W * NP;
+    unsigned *FOk = reinterpret_cast<unsigned *>(tv + (size_t)W * Rm * Km);
+    unsigned *hsOk = FOk + (size_t)(Cm + 1) * (W + 1);
+    const unsigned char *yt = v.ytab + (size_t)yi * v.yrow;
+    r = yt[0];
+    for (int j = lane; j <= r; j += blockDim.x) Yl[j] = yt[1 + j];
+    for (size_t e = lane; e < F; e += blockDim.x) FT[e] = e == 0 ? V(0) : kNo;
+    for (int e = lane; e < (Cm + 1) * (W + 1); e += blockDim.x) FOk[e] = e == 0;
+    __syncthreads();
+    const SmallDiv divR((unsigned)r), divNP((unsigned)NP);
+    for (int x = 1; x <= W; x++) {
+        for (int e = lane; e < x * r; e += blockDim.x) {
+            unsigned xp, j;
+            divR.divmod((unsigned)e, xp, j);
+            const size_t tb = (((size_t)wi * S + sidx(xp, x, W)) * R2 + ridx(Yl[j], Yl[j + 1], v.H)) * Km;
+            const size_t lb = ((size_t)xp * Rm + j) * Km;
+            for (int k = 0; k < Km; k++) {
+                tv[lb + k] = narrow(w.tT[tb + k]);
+            }
+        }
+        for (int e = lane; e < x * NP; e += blockDim.x) {
+            unsigned xp, K;
+            divNP.divmod((unsigned)e, xp, K);
+            hsA[e] = K == 0 ? V(0) : kNo;
+        }
+        for (int xp = lane; xp < x; xp += blockDim.x) hsOk[xp] = 0;
+        __syncthreads();
+        V *cur = hsA, *nxt = hsB;
+        for (int j = 0; j < r; j++) {
+            for (int e = lane; e < x * NP; e += blockDim.x) {
+                unsigned xp, K;
+                divNP.divmod((unsigned)e, xp, K);
+                const V *tj = tv + ((size_t)xp * Rm + j) * Km;
+                const V *row = cur + (size_t)xp * NP;
+                V best = kNo;
+                const int kmax = (int)K < Km ? (int)K : Km;
+                for (int k = 1; k <= kmax; k++) {
+                    const V a = row[K - k], b = tj[k - 1];
+                    const V t = a > b ? a : b;
+                    best = t < best ? t : best;
+                }
+                if (best > bt) best = kNo;
+                nxt[e] = best;
+                if (j == r - 1 && best != kNo) hsOk[xp] = 1;
+            }
+            __syncthreads();
+            V *tmp = cur; cur = nxt; nxt = tmp;
+        }
+        // column DP: one (i, x') pair per lane, all n at once
+        const SmallDiv divX((unsigned)x);
+        for (int e = lane; e < Cm * x; e += blockDim.x) {
+            unsigned i1, xpu;
+            divX.divmod((unsigned)e, i1, xpu);
+            const int i = 1 + (int)i1, xp = (int)xpu;
+            if (xp < i - 1 || !hsOk[xp] || !FOk[(i - 1) * (W + 1) + xp]) continue;
+            const V *h = cur + (size_t)xp * NP;
+            const V *f = FT + ((size_t)(i - 1) * (W + 1) + xp) * NP;
+            bool any = false;
+            for (int n = 1; n <= N; n++) {
+                V best = kNo;
+                for (int K = 1; K <= n; K++) {
+                    const V a = f[n - K], b = h[K];
+                    const V t = a > b ? a : b;
+                    best = t < best ? t : best;
+                }
+                if (best <= bt) {
+                    atomicMin(FT + ((size_t)i * (W + 1) + x) * NP + n, best);
+                    any = true;
+                }
+            }
+            if (any) FOk[i * (W + 1) + x] = 1;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        V best = kNo;
+        for (int c = 1; c <= Cm; c++) {
+            const V t = FT[((size_t)c * (W + 1) + W) * NP + N];
+            best = t < best ? t : best;
+        }
+        *result = best == kNo ? kInf : (long long)best;
+    }
+}
+
+__host__ __device__ inline size_t unit1_lds_bytes(int W, int N, int Cm, int Rm, int Km, int vbytes)
+{
+    const size_t F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    return vbytes * (F + 2 * (size_t)W * (N + 1) + (size_t)W * Rm * Km) + 4 * ((size_t)(Cm + 1) * (W + 1) + W);
+}
+
+template <int STEP, class V1 = unsigned long long>
 __global__ void __launch_bounds__(64)
 k_lit_units(LitView v, LitWs w)
 {
@@ -364,8 +511,17 @@ k_lit_units(LitView v, LitWs w)
         const unsigned long long qb = __atomic_load_n(&w.hdr[3], __ATOMIC_RELAXED);
         if (qb != kNone) bq = (long long)qb;
     }
-    const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, STEP, false);
     int r = 0;
+    if (STEP == 1) {
+        __shared__ long long res1;
+        if ((w.hdr[4] != 0) != (sizeof(V1) == 4)) return;     // the other launch takes this frame
+        unit_dp1<V1>(v, w, u, lds_raw, Yl, r, bt, &res1);
+        if (threadIdx.x != 0) return;
+        w.uT[u] = res1;                                 // the unit's own minimum (kInf if pruned)
+        if (res1 != kInf) atomicMin(w.hdr, (unsigned long long)res1);
+        return;
+    }
+    const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, v.Rm, v.Km, STEP, false);
     unit_dp<STEP, false>(v, w, u, L, Yl, r, bt, bq);
     if (threadIdx.x != 0) return;
     long long ct = kInf, cq = kInf;
@@ -375,15 +531,10 @@ k_lit_units(LitView v, LitWs w)
         const long long t = L.FT[f], q = STEP == 2 ? L.FQ[f] : 0;
         if (t != kInf && better<STEP>(q, t, cq, ct)) { ct = t; cq = q; bc = c; }
     }
-    if (STEP == 1) {
-        w.uT[u] = ct;                                   // the unit's own minimum (kInf if pruned)
-        if (ct != kInf) atomicMin(w.hdr, (unsigned long long)ct);
-    } else {
-        w.uQ[u] = cq;
-        w.uT[u] = ct;
-        w.uC[u] = bc;
-        if (ct != kInf) atomicMin(w.hdr + 3, (unsigned long long)cq);
-    }
+    w.uQ[u] = cq;
+    w.uT[u] = ct;
+    w.uC[u] = bc;
+    if (ct != kInf) atomicMin(w.hdr + 3, (unsigned long long)cq);
 }
 
 // Lexicographic minimum of (Q, T~, unit) over the units.
@@ -429,7 +580,8 @@ k_lit_pick(LitView v, LitWs w)
 __host__ __device__ inline size_t final_lds_bytes(int W, int H, int N, int Cm, int Rm, int Km)
 {
     const size_t knap = (size_t)(Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
-    return unit_lds_bytes(W, N, Cm, 2, true) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile;
+    return unit_lds_bytes(W, N, Cm, Rm, Km, 2, true) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile +
+           (size_t)Rm * Cm;
 }
 
 __global__ void __launch_bounds__(64)
@@ -439,21 +591,21 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
     __shared__ int Yl[kMaxH + 1];
     __shared__ __align__(16) trs_result res;
     __shared__ int cx[kMaxW + 1], ck[kMaxW + 1];
-    __shared__ unsigned char tcnt[kMaxH][kMaxW];
     const int lane = threadIdx.x;
     const int W = v.W, H = v.H, N = v.N, Km = v.Km;
     {
         unsigned *z = reinterpret_cast<unsigned *>(&res);
         for (size_t e = lane; e < sizeof(trs_result) / 4; e += blockDim.x) z[e] = 0;
     }
-    const UnitLds L = unit_lds(lds_raw, W, N, v.Cm, 2, true);
-    unsigned char *extra = lds_raw + unit_lds_bytes(W, N, v.Cm, 2, true);
+    const UnitLds L = unit_lds(lds_raw, W, N, v.Cm, v.Rm, Km, 2, true);
+    unsigned char *extra = lds_raw + unit_lds_bytes(W, N, v.Cm, v.Rm, Km, 2, true);
     const size_t knap = (size_t)(v.Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
     long long *kT = reinterpret_cast<long long *>(extra), *kQ = kT + knap;
     unsigned char *kC = reinterpret_cast<unsigned char *>(kQ + knap);
     long long *fT = reinterpret_cast<long long *>(extra + ((17 * knap + 15) & ~size_t(15)));
     long long *fQ = fT + tile;
     int *fA = reinterpret_cast<int *>(fQ + tile);
+    unsigned char *tcnt = reinterpret_cast<unsigned char *>(fA + tile);    // [row][column] slice counts
     __syncthreads();
     const unsigned long long tmin = w.hdr[0];
     const bool feasible = tmin != kNone && w.hdr[1] != kNone;
@@ -554,8 +706,8 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
                     }
                 }
                 for (int j = r, K = ck[i]; j > 0; j--) {
-                    tcnt[j - 1][i] = kC[j * (N + 1) + K];
-                    K -= tcnt[j - 1][i];
+                    tcnt[(j - 1) * v.Cm + i] = kC[j * (N + 1) + K];
+                    K -= tcnt[(j - 1) * v.Cm + i];
                 }
             }
             // tiles in raster order, slices top to bottom: split rows from the tile DP's argmins
@@ -563,7 +715,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
             long long tsel = 0, qsel = 0;
             for (int j = 0; j < r; j++)
                 for (int i = 0; i < c; i++) {
-                    const int kq = tcnt[j][i];
+                    const int kq = tcnt[j * v.Cm + i];
                     const int y0 = Yl[j], y1 = Yl[j + 1], x0 = cx[i], x1 = cx[i + 1];
                     auto at = [&](int q, int y) { return (size_t)q * (H + 1) + y; };
                     for (int q = 0; q <= kq; q++)
@@ -680,8 +832,8 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
             pl.row_yy[2 * q] = (unsigned char)y0;
             pl.row_yy[2 * q + 1] = (unsigned char)y1;
         }
-    if (unit_lds_bytes(pl.W, pl.N, pl.Cm, 2, false) > kLdsLimit ||
-        final_lds_bytes(pl.W, pl.H, pl.N, pl.Cm, pl.Rm, pl.Km) > kLdsLimit - 8 * 1024 ||
+    if (unit_lds_bytes(pl.W, pl.N, pl.Cm, pl.Rm, pl.Km, 2, false) > kLdsLimit - 1024 ||
+        final_lds_bytes(pl.W, pl.H, pl.N, pl.Cm, pl.Rm, pl.Km) > kLdsLimit - 4 * 1024 ||
         (size_t)7 * 8 * pl.R2 > kLdsLimit)
         return TRS_ENOTIMPL;
     // windows: distinct RS areas a with N a <= A_total < k N a (all areas when k = 0: one window)
@@ -921,11 +1073,14 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
         const dim3 gt((unsigned)(v.n_win * v.S)), gu((unsigned)v.n_units);
         hipLaunchKernelGGL(k_lit_tiles<1>, gt, dim3(256), tl, stream, v, w);
         mark(2);
-        hipLaunchKernelGGL(k_lit_units<1>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, 1, false), stream, v, w);
+        hipLaunchKernelGGL((k_lit_units<1, unsigned>), gu, dim3(64),
+                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 4), stream, v, w);
+        hipLaunchKernelGGL((k_lit_units<1, unsigned long long>), gu, dim3(64),
+                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 8), stream, v, w);
         mark(3);
         hipLaunchKernelGGL(k_lit_tiles<2>, gt, dim3(256), tl, stream, v, w);
         mark(4);
-        hipLaunchKernelGGL(k_lit_units<2>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, 2, false), stream, v, w);
+        hipLaunchKernelGGL(k_lit_units<2>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 2, false), stream, v, w);
         mark(5);
         hipLaunchKernelGGL(k_lit_pick, dim3(1), dim3(1024), 0, stream, v, w);
         mark(6);

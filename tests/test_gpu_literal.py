@@ -72,3 +72,21 @@ def test_literal_search_4k_matches_stored_oracle_result(orc):
     # the ladder space is a subset: its T~min cannot be lower
     lad = orc.search(w, h, orc.make_params(8, 6, 4, 4, lam=(1, 10)), cost, f["s1"], f["s2"])
     assert got["t_min"] <= lad["t_min"]
+
+
+@pytest.mark.parametrize("w,h,N,C,R,K,lam", [(640, 512, 3, 3, 3, 2, (1, 10)), (1024, 768, 5, 3, 3, 3, (-1, 1)),
+                                             (1920, 1080, 8, 6, 4, 4, (3, 10))])
+def test_literal_search_with_totals_beyond_32_bits_matches_oracle(orc, w, h, N, C, R, K, lam):
+    """Predicted times near 2^30 per CTU push the frame total past 2^32, which takes the
+    64-bit form of the step-1 units; the result still equals the oracle's."""
+    import numpy as np
+    luma = synth.make_frame(w, h, 9)
+    f = orc.features(luma)
+    W, H = orc.ctu_dims(w, h)
+    rng = np.random.default_rng(11)
+    cost = rng.integers(1 << 29, 1 << 30, W * H, dtype=np.int64).astype(np.uint32)
+    assert int(cost.astype(np.int64).sum()) >= (1 << 32)
+    p = B.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1)
+    ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], f["s2"])
+    got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], f["s2"])
+    assert_same_result(got, ref, f"{w}x{h} N {N} wide totals")
