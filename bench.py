@@ -272,7 +272,6 @@ def main():
     # max and add (5); per candidate the bound test and key compare (6); per record slice
     # three rectangle sums, the exact floor(S1^2 / n) and the sums (40)
     ops2 = step2_frac * (5 * stats["tile_lookups"] + 6 * stats["feasible"] + 40 * stats["record_slices"])
-    pre = "k_search_batch" if batched else "k_search"
     kblock = (block or 256) if batched else (params.sched_block or 256)
     fk = "k_features_batch<128>" if batched else "k_features<128>"
     kernels = {
@@ -281,7 +280,7 @@ def main():
         (f"k_step1_units<{kblock}> (step 1)" if batched else f"k_search<{kblock}, false> (step 1)"): {
             "bound": "alu", "avg_ms": kms["step1"], "work": ops1 * launch_frames,
             "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
-        f"{pre}<{kblock}, true> (step 2)": {
+        (f"k_step2_live<{kblock}> (step 2)" if batched else f"k_search<{kblock}, true> (step 2)"): {
             "bound": "alu", "avg_ms": kms["step2"], "work": ops2 * launch_frames,
             "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "scale": 1e12},
     }
@@ -813,6 +812,18 @@ def run_literal(args):
     ach = ops[dom] / (st[dom] * 1e-3) / 1e12
     res = [B.read_result(out[f]) for f in range(1, F + 1)]
     log("stages (ms per frame): " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
+    # the same frames over the ladder space (the default search) for comparison
+    lad_p = B.make_params(N, C, R, K, lam=lam)
+    lws = torch.empty(B.trs_search_workspace(frame, lad_p), dtype=torch.uint8, device="cuda")
+    lout = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    better_t = better_q = 0
+    for f in range(1, F + 1):
+        B.trs_search(frame, lad_p, cost[f], feats[f]["s1"], feats[f]["s2"], lws, lout)
+        lr = B.read_result(lout)
+        assert res[f - 1]["t_min"] <= lr["t_min"], "literal T~min above the ladder's"
+        better_t += res[f - 1]["t_min"] < lr["t_min"]
+        better_q += res[f - 1]["q_sel"] < lr["q_sel"]
+    log(f"literal vs ladder: lower T~min on {better_t}/{F} frames, lower Q on {better_q}/{F}")
 
     cpu, parity = None, "not checked (--no-cpu-baseline)"
     if not args.no_cpu_baseline:
@@ -849,6 +860,7 @@ def run_literal(args):
                      "achieved": round(ach, 3), "peak": PEAK_ALU_TOPS, "unit": "T lane-ops/s",
                      "frac": round(ach / PEAK_ALU_TOPS, 4), "traffic": None},
         "t_min_frames": [r["t_min"] for r in res],
+        "literal_better_than_ladder": {"t_min": better_t, "q": better_q, "frames": F},
         "parity": parity,
         "cpu_baseline": cpu,
     }
