@@ -594,7 +594,7 @@ def run_mlp(args):
     T = torch.rand(pool, generator=g, device="cuda") * 3
     m = TimeMLP(seed=0)
     m.fit_norm(X)
-    opt = torch.optim.Adam(m.parameters(), lr=1e-3, fused=True)
+    opt = torch.optim.Adam(m.parameters(), lr=1e-3, fused=True, capturable=True)
     idx = [torch.randint(0, pool, (nb,), generator=g, device="cuda") for _ in range(16)]
     xs = [X[i].contiguous() for i in idx]
     ts = [T[i].contiguous() for i in idx]
@@ -606,16 +606,37 @@ def run_mlp(args):
         loss.backward()
         opt.step()
 
-    for k in range(max(args.warmup, 1)):
-        step(k)
+    # warm-up on a side stream (the optimiser state is created here), then eager timing
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for k in range(max(args.warmup, 1)):
+            step(k)
+    torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(k)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el_eager = time.perf_counter() - t0
+    sps_eager = nb * args.steps / el_eager
+    # the same steps as one HIP graph of 16 steps (one per resident batch), replayed: the
+    # host's launch overhead leaves the timed region
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for k in range(16):
+            step(k)
+    graph.replay()
+    torch.cuda.synchronize()
+    reps = max(1, (args.steps + 15) // 16)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / (16 * reps) * args.steps
     sps = nb * args.steps / el
-    log(f"mlp training: {sps / 1e6:.2f} M samples/s ({el / args.steps * 1e3:.3f} ms/step of {nb})")
+    log(f"mlp training: {sps / 1e6:.2f} M samples/s graph-replayed ({el / args.steps * 1e3:.3f} ms/step of {nb}); "
+        f"eager {sps_eager / 1e6:.2f} M samples/s")
 
     # kernel durations with events on the launching stream, at the training batch size
     ws = [p.detach() for p in m.parameters()]
@@ -700,6 +721,8 @@ def run_mlp(args):
         "data": "synthetic",
         "config": {"workload": f"10-64-64-1 GELU perceptron, batches of {nb} samples from a resident "
                                f"pool of {pool} synthetic inputs", "batch": nb},
+        "eager_value": round(sps_eager, 1),
+        "timing": f"{16 * reps} training steps as {reps} replays of a 16-step HIP graph",
         "kernel_ms": {"forward": round(fwd_ms, 5), "backward": round(bwd_ms, 5)},
         "roofline": {"bound": "alu", "kernel": "k_mlp_fwd", "achieved": round(fwd_tf, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(fwd_tf / PEAK_FP32_TFLOPS, 4),

@@ -4,10 +4,11 @@
 //
 //   k_mlp_inputs      the 10 raw inputs per CTU from the method's own features and times
 //   k_mlp_fwd         two lanes per sample, weights in LDS; optionally keeps z1, z2
-//   k_mlp_bwd_data    per sample (two lanes) dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1)
+//   k_mlp_bwd_data    per sample (two lanes) dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1),
+//                     and the activations gelu(z1), gelu(z2) from the same erf
 //   k_mlp_bwd_w       weight gradients: each work-group sums its sample chunk into one
 //                     partial (entries spread over threads, samples staged in LDS tiles)
-//   k_mlp_reduce      partials summed in a fixed order, one wave per entry (deterministic)
+//   k_mlp_reduce*     partials summed in two fixed-order passes, one thread per entry
 //   k_mlp_cost        prediction -> u32 microseconds, or the plain blend per CTU when the
 //                     prediction is not finite or an input is outside the training range
 #include <hip/hip_runtime.h>
@@ -24,10 +25,13 @@ constexpr float kInvSqrt2Pi = 0.39894228040143268f;
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * kInvSqrt2)); }
 
-// d/dx gelu(x) = Phi(x) + x phi(x)
-__device__ __forceinline__ float gelu_grad(float x)
+// gelu(x) and d/dx gelu(x) = Phi(x) + x phi(x) from one erf, with the same operations (and so
+// the same values) as gelu() above
+__device__ __forceinline__ void gelu_and_grad(float x, float &g, float &d)
 {
-    return 0.5f * (1.0f + erff(x * kInvSqrt2)) + x * kInvSqrt2Pi * expf(-0.5f * x * x);
+    const float e = erff(x * kInvSqrt2);
+    g = 0.5f * x * (1.0f + e);
+    d = 0.5f * (1.0f + e) + x * kInvSqrt2Pi * expf(-0.5f * x * x);
 }
 
 struct Weights {
@@ -96,14 +100,23 @@ k_mlp_fwd(Weights wt, trs_mlp_norm nm, const float *__restrict__ x, long long n,
     float xn[kIn];
 #pragma unroll
     for (int i = 0; i < kIn; i++) xn[i] = (x[sc * kIn + i] - nm.mean[i]) * nm.inv_std[i];
-    float h1[kHid];
+    // first layer: this lane's half of the outputs, then the partner's half by DPP
+    constexpr int KH = kHid / 2;
+    float mine[KH], h1[kHid];
 #pragma unroll
-    for (int j = 0; j < kHid; j++) {
+    for (int jj = 0; jj < KH; jj++) {
+        const int j = KH * hf + jj;
         float z = sb1[j];
 #pragma unroll
         for (int i = 0; i < kIn; i++) z = fmaf(sW1[j * kIn + i], xn[i], z);
-        if (z1o && ok && (j >> 5) == hf) z1o[(long long)j * n + s] = z;
-        h1[j] = gelu(z);
+        if (z1o && ok) z1o[(long long)j * n + s] = z;
+        mine[jj] = gelu(z);
+    }
+#pragma unroll
+    for (int jj = 0; jj < KH; jj++) {
+        const float other = pair_swap(mine[jj]);
+        h1[jj] = hf ? other : mine[jj];
+        h1[KH + jj] = hf ? mine[jj] : other;
     }
     float part = 0.0f;
     for (int kk = 0; kk < kHid / 2; kk++) {
@@ -124,7 +137,7 @@ k_mlp_fwd(Weights wt, trs_mlp_norm nm, const float *__restrict__ x, long long n,
 __global__ void __launch_bounds__(256)
 k_mlp_bwd_data(Weights wt, const float *__restrict__ z1, const float *__restrict__ z2,
                const float *__restrict__ dy, long long n, float *__restrict__ dz1o,
-               float *__restrict__ dz2o)
+               float *__restrict__ dz2o, float *__restrict__ h1o, float *__restrict__ h2o)
 {
     __shared__ float sW1[kHid * kIn], sb1[kHid], sW2[kHid * kHid], sb2[kHid], sW3[kHid], sb3[1];
     load_weights(wt, sW1, sb1, sW2, sb2, sW3, sb3);
@@ -140,8 +153,13 @@ k_mlp_bwd_data(Weights wt, const float *__restrict__ z1, const float *__restrict
 #pragma unroll
     for (int kk = 0; kk < KH; kk++) {
         const int k = KH * hf + kk;
-        dz2[kk] = gy * sW3[k] * gelu_grad(z2[(long long)k * n + sc]);
-        if (ok) dz2o[(long long)k * n + s] = dz2[kk];
+        float g, d;
+        gelu_and_grad(z2[(long long)k * n + sc], g, d);
+        dz2[kk] = gy * sW3[k] * d;
+        if (ok) {
+            dz2o[(long long)k * n + s] = dz2[kk];
+            h2o[(long long)k * n + s] = g;
+        }
     }
     for (int j = 0; j < kHid; j++) {
         float a = 0.0f;
@@ -149,7 +167,12 @@ k_mlp_bwd_data(Weights wt, const float *__restrict__ z1, const float *__restrict
         for (int kk = 0; kk < KH; kk++) a = fmaf(sW2[(KH * hf + kk) * kHid + j], dz2[kk], a);
         const float o = pair_swap(a);
         const float tot = hf == 0 ? a + o : o + a;
-        if (ok && (j >> 5) == hf) dz1o[(long long)j * n + s] = tot * gelu_grad(z1[(long long)j * n + s]);
+        if (ok && (j >> 5) == hf) {
+            float g, d;
+            gelu_and_grad(z1[(long long)j * n + s], g, d);
+            dz1o[(long long)j * n + s] = tot * d;
+            h1o[(long long)j * n + s] = g;
+        }
     }
 }
 
@@ -169,13 +192,14 @@ __device__ __forceinline__ int small_to_entry(int q)
 }
 
 __global__ void __launch_bounds__(256)
-k_mlp_bwd_w(trs_mlp_norm nm, const float *__restrict__ x, const float *__restrict__ z1,
-            const float *__restrict__ z2, const float *__restrict__ dz1,
+k_mlp_bwd_w(trs_mlp_norm nm, const float *__restrict__ x, const float *__restrict__ h1,
+            const float *__restrict__ h2, const float *__restrict__ dz1,
             const float *__restrict__ dz2, const float *__restrict__ dy, long long n,
             int chunk, float *__restrict__ partial)
 {
-    __shared__ float tx[kTile][kIn], th1[kTile][kHid], th2[kTile][kHid];
-    __shared__ float tdz1[kTile][kHid], tdz2[kTile][kHid], tdy[kTile];
+    // rows padded by one float: the staging writes walk r (samples) fastest
+    __shared__ float tx[kTile][kIn], th1[kTile][kHid + 1], th2[kTile][kHid + 1];
+    __shared__ float tdz1[kTile][kHid + 1], tdz2[kTile][kHid + 1], tdy[kTile];
     const int tid = threadIdx.x;
     const int k2 = tid >> 2, j2 = (tid & 3) * 16;
     float a2[16];
@@ -189,11 +213,12 @@ k_mlp_bwd_w(trs_mlp_norm nm, const float *__restrict__ x, const float *__restric
         __syncthreads();
 #pragma unroll 1
         for (int e = tid; e < kTile * kHid; e += blockDim.x) {
-            const int r = e / kHid, j = e - r * kHid;
+            // consecutive threads read consecutive samples of one row j of the [64][n] arrays
+            const int j = e / kTile, r = e - j * kTile;
             const bool in = r < nt;
             const long long s = t0 + r;
-            th1[r][j] = in ? gelu(z1[(long long)j * n + s]) : 0.0f;
-            th2[r][j] = in ? gelu(z2[(long long)j * n + s]) : 0.0f;
+            th1[r][j] = in ? h1[(long long)j * n + s] : 0.0f;
+            th2[r][j] = in ? h2[(long long)j * n + s] : 0.0f;
             tdz1[r][j] = in ? dz1[(long long)j * n + s] : 0.0f;
             tdz2[r][j] = in ? dz2[(long long)j * n + s] : 0.0f;
         }
@@ -246,18 +271,29 @@ struct Grads {
     float *w1, *b1, *w2, *b2, *w3, *b3;
 };
 
-// One wave per gradient entry: lane l sums partials l, l + 64, .. in order, then a fixed
-// butterfly adds the lanes, so the result repeats exactly.
+// The partials are summed in two fixed-order passes, one thread per gradient entry (lanes read
+// consecutive entries of a partial, so loads are coalesced): pass 1 sums groups of kGroup
+// consecutive partials, pass 2 the group sums in order.  The result repeats exactly.
+constexpr int kGroup = 16;
+
 __global__ void __launch_bounds__(256)
-k_mlp_reduce(const float *__restrict__ partial, int n_part, Grads g)
+k_mlp_reduce_groups(const float *__restrict__ partial, int n_part, float *__restrict__ grp)
 {
-    const int e = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (e >= kEntries) return;                         // the whole wave leaves together
+    const int e = blockIdx.x * blockDim.x + threadIdx.x, g = blockIdx.y;
+    if (e >= kEntries) return;
+    const int p1 = min(n_part, (g + 1) * kGroup);
     float a = 0.0f;
-    for (int p = lane; p < n_part; p += 64) a += partial[(long long)p * kEntries + e];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m, 64);
-    if (lane != 0) return;
+    for (int p = g * kGroup; p < p1; p++) a += partial[(long long)p * kEntries + e];
+    grp[(long long)g * kEntries + e] = a;
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_reduce(const float *__restrict__ grp, int n_grp, Grads g)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kEntries) return;
+    float a = 0.0f;
+    for (int q = 0; q < n_grp; q++) a += grp[(long long)q * kEntries + e];
     int o = e;
     if (o < kHid * kIn) { g.w1[o] = a; return; }
     o -= kHid * kIn;
@@ -325,8 +361,8 @@ hipError_t launch_mlp_forward(const trs_mlp &m, const trs_mlp_norm &nm, const fl
 size_t mlp_backward_workspace(long long n)
 {
     const long long chunk = mlp_chunk(n);
-    const long long parts = (n + chunk - 1) / chunk;
-    return (size_t)(2 * kHid * n + parts * kEntries) * sizeof(float) + 512;
+    const long long parts = (n + chunk - 1) / chunk, groups = (parts + kGroup - 1) / kGroup;
+    return (size_t)(4 * kHid * n + (parts + groups) * kEntries) * sizeof(float) + 512;
 }
 
 long long mlp_chunk(long long n)
@@ -344,15 +380,20 @@ hipError_t launch_mlp_backward(const trs_mlp &m, const trs_mlp_norm &nm, const f
     const Weights w{m.w1, m.b1, m.w2, m.b2, m.w3, m.b3};
     float *dz1 = reinterpret_cast<float *>(ws);
     float *dz2 = dz1 + kHid * n;
-    float *part = dz2 + kHid * n;
+    float *h1 = dz2 + kHid * n;
+    float *h2 = h1 + kHid * n;
+    float *part = h2 + kHid * n;
     const long long chunk = mlp_chunk(n);
-    const int parts = (int)((n + chunk - 1) / chunk);
+    const int parts = (int)((n + chunk - 1) / chunk), groups = (parts + kGroup - 1) / kGroup;
+    float *grp = part + (long long)parts * kEntries;
     hipLaunchKernelGGL(k_mlp_bwd_data, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, w, z1, z2,
-                       dy, n, dz1, dz2);
-    hipLaunchKernelGGL(k_mlp_bwd_w, dim3(parts), dim3(256), 0, s, nm, x, z1, z2, dz1, dz2, dy, n,
+                       dy, n, dz1, dz2, h1, h2);
+    hipLaunchKernelGGL(k_mlp_bwd_w, dim3(parts), dim3(256), 0, s, nm, x, h1, h2, dz1, dz2, dy, n,
                        (int)chunk, part);
     const Grads gg{g.w1, g.b1, g.w2, g.b2, g.w3, g.b3};
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kEntries + 3) / 4), dim3(256), 0, s, part, parts, gg);
+    const unsigned eb = (unsigned)((kEntries + 255) / 256);
+    hipLaunchKernelGGL(k_mlp_reduce_groups, dim3(eb, (unsigned)groups), dim3(256), 0, s, part, parts, grp);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(eb), dim3(256), 0, s, grp, groups, gg);
     return hipGetLastError();
 }
 
