@@ -90,3 +90,17 @@ def test_literal_search_with_totals_beyond_32_bits_matches_oracle(orc, w, h, N, 
     ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], f["s2"])
     got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], f["s2"])
     assert_same_result(got, ref, f"{w}x{h} N {N} wide totals")
+
+
+def test_literal_search_ctu64_matches_oracle(orc):
+    """CTU 64 (a 30 x 17 grid on 1080p, finer areas: more windows)."""
+    w, h, cs = 1920, 1080, 64
+    luma = synth.make_frame(w, h, 5)
+    f = orc.features(luma, cs)
+    W, H = orc.ctu_dims(w, h, cs)
+    prev = synth.ctu_times(f["tex"], synth.ar1_eps(W * H, 1, 5)[0])
+    cost, _ = orc.cost_map(f["tex"], prev)
+    p = B.make_params(4, 3, 3, 2, lam=(1, 10), dtile=-1, drs=-1)
+    ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], f["s2"], cs=cs)
+    got = gpu_literal(B.make_frame(w, h, ctu_size=cs), p, cost, f["s1"], f["s2"])
+    assert_same_result(got, ref, "1080p CTU 64")
