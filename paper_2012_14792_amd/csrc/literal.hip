@@ -383,7 +383,7 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
 // value type: 32-bit when the frame's total predicted time is below 2^32 - 1 (every region sum
 // then fits), else 64-bit; its largest value is the "none" sentinel, which max() propagates and
 // min() ignores, so no separate test is needed.
-template <class V>
+template <class V, int NB>
 __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char *raw, int *Yl, int &r,
                          long long bt_in, long long *result)
 {
@@ -456,15 +456,23 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
             if (xp < i - 1 || !hsOk[xp] || !FOk[(i - 1) * (W + 1) + xp]) continue;
             const V *h = cur + (size_t)xp * NP;
             const V *f = FT + ((size_t)(i - 1) * (W + 1) + xp) * NP;
+            // both rows in registers (NB >= N, entries past N are "none"), loops unrolled
+            V fr[NB + 1], hr[NB + 1];
+#pragma unroll
+            for (int q = 0; q <= NB; q++) {
+                fr[q] = q <= N ? f[q] : kNo;
+                hr[q] = q <= N ? h[q] : kNo;
+            }
             bool any = false;
-            for (int n = 1; n <= N; n++) {
+#pragma unroll
+            for (int n = 1; n <= NB; n++) {
                 V best = kNo;
+#pragma unroll
                 for (int K = 1; K <= n; K++) {
-                    const V a = f[n - K], b = h[K];
-                    const V t = a > b ? a : b;
+                    const V t = fr[n - K] > hr[K] ? fr[n - K] : hr[K];
                     best = t < best ? t : best;
                 }
-                if (best <= bt) {
+                if (n <= N && best <= bt) {
                     atomicMin(FT + ((size_t)i * (W + 1) + x) * NP + n, best);
                     any = true;
                 }
@@ -515,7 +523,9 @@ k_lit_units(LitView v, LitWs w)
     if (STEP == 1) {
         __shared__ long long res1;
         if ((w.hdr[4] != 0) != (sizeof(V1) == 4)) return;     // the other launch takes this frame
-        unit_dp1<V1>(v, w, u, lds_raw, Yl, r, bt, &res1);
+        if (v.N <= 8) unit_dp1<V1, 8>(v, w, u, lds_raw, Yl, r, bt, &res1);
+        else if (v.N <= 16) unit_dp1<V1, 16>(v, w, u, lds_raw, Yl, r, bt, &res1);
+        else unit_dp1<V1, kMaxN>(v, w, u, lds_raw, Yl, r, bt, &res1);
         if (threadIdx.x != 0) return;
         w.uT[u] = res1;                                 // the unit's own minimum (kInf if pruned)
         if (res1 != kInf) atomicMin(w.hdr, (unsigned long long)res1);
