@@ -3,8 +3,8 @@
 // conclusion names a better CTU time estimator as future work).
 //
 //   k_mlp_inputs      the 10 raw inputs per CTU from the method's own features and times
-//   k_mlp_fwd         two lanes per sample, weights in LDS; optionally keeps z1, z2
-//   k_mlp_bwd_data    per sample (two lanes) dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1),
+//   k_mlp_fwd         four lanes per sample, weights in LDS; optionally keeps z1, z2
+//   k_mlp_bwd_data    per sample (four lanes) dz2 = dy W3 * gelu'(z2), dz1 = (W2^T dz2) * gelu'(z1),
 //                     and the activations gelu(z1), gelu(z2) from the same erf
 //   k_mlp_bwd_w       weight gradients: each work-group sums its sample chunk into one
 //                     partial (entries spread over threads, samples staged in LDS tiles)
@@ -38,19 +38,6 @@ struct Weights {
     const float *w1, *b1, *w2, *b2, *w3, *b3;
 };
 
-__device__ __forceinline__ void load_weights(const Weights &w, float *sW1, float *sb1, float *sW2,
-                                             float *sb2, float *sW3, float *sb3)
-{
-    for (int i = threadIdx.x; i < kHid * kIn; i += blockDim.x) sW1[i] = w.w1[i];
-    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x) sW2[i] = w.w2[i];
-    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
-        sb1[i] = w.b1[i];
-        sb2[i] = w.b2[i];
-        sW3[i] = w.w3[i];
-    }
-    if (threadIdx.x == 0) sb3[0] = w.b3[0];
-}
-
 __global__ void __launch_bounds__(256)
 k_mlp_inputs(int W, int H, int cs, int w, int h, const uint32_t *__restrict__ tex,
              const uint32_t *__restrict__ var, const uint32_t *__restrict__ mean,
@@ -75,103 +62,138 @@ k_mlp_inputs(int W, int H, int cs, int w, int h, const uint32_t *__restrict__ te
     o[9] = n / (float)(cs * cs);
 }
 
-// Lanes 2i and 2i + 1 work on one sample: pair_swap returns the partner lane's value.
-__device__ __forceinline__ float pair_swap(float v)
+// Lanes 4i .. 4i + 3 (one DPP quad) work on one sample; quarter q of the quad owns hidden units
+// 16 q .. 16 q + 15 of each layer.  quad_from<m> returns the value of lane q ^ m of the quad.
+constexpr int kLanes = 4, kQ = kHid / kLanes;
+
+template <int M>
+__device__ __forceinline__ float quad_from(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF,
-                                                                 0xF, false));   // quad_perm 1,0,3,2
+    constexpr int ctrl = M == 1 ? 0xB1 : M == 2 ? 0x4E : 0x1B;   // quad_perm [1,0,3,2] [2,3,0,1] [3,2,1,0]
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF,
+                                                                 0xF, false));
 }
 
-// Two lanes per sample: both evaluate the first layer; the lane of half hf takes the second
-// layer's outputs 32 hf .. 32 hf + 31 and its share of the output sum, and the pair adds the
-// two shares (half 0's first, so every lane forms the same sum).
+// Sum of one value per quad lane in the fixed order (v0 + v1) + (v2 + v3); every lane gets it.
+__device__ __forceinline__ float quad_sum(float v, int q)
+{
+    const float o1 = quad_from<1>(v);
+    const float pair = (q & 1) ? o1 + v : v + o1;                 // lanes 0,1: v0 + v1; 2,3: v2 + v3
+    const float o2 = quad_from<2>(pair);
+    return (q & 2) ? o2 + pair : pair + o2;
+}
+
+// LDS copies of W1 and W2 for the four-lane kernels: row r = 16 q + kk is stored at position
+// 4 kk + q (the four quarters' rows side by side) and W2 rows are padded to 65 floats, so the
+// four addresses one load instruction reads from a quad lie in four different banks.
+constexpr int kW2Pitch = kHid + 1;
+
+__device__ __forceinline__ int qrow(int r) { return (r % kQ) * kLanes + r / kQ; }
+
+__device__ __forceinline__ void load_weights_q(const Weights &w, float *sW1, float *sb1, float *sW2,
+                                               float *sb2, float *sW3, float *sb3)
+{
+    for (int i = threadIdx.x; i < kHid * kIn; i += blockDim.x) sW1[qrow(i / kIn) * kIn + i % kIn] = w.w1[i];
+    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x)
+        sW2[qrow(i / kHid) * kW2Pitch + i % kHid] = w.w2[i];
+    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+        sb1[i] = w.b1[i];
+        sb2[i] = w.b2[i];
+        sW3[i] = w.w3[i];
+    }
+    if (threadIdx.x == 0) sb3[0] = w.b3[0];
+}
+
+// Four lanes per sample: each evaluates its quarter of the first layer, the quad exchanges the
+// quarters, each evaluates its quarter of the second layer and its share of the output, and the
+// quad adds the shares in a fixed order.
 __global__ void __launch_bounds__(256)
 k_mlp_fwd(Weights wt, trs_mlp_norm nm, const float *__restrict__ x, long long n,
           float *__restrict__ y, float *__restrict__ z1o, float *__restrict__ z2o)
 {
-    __shared__ float sW1[kHid * kIn], sb1[kHid], sW2[kHid * kHid], sb2[kHid], sW3[kHid], sb3[1];
-    load_weights(wt, sW1, sb1, sW2, sb2, sW3, sb3);
+    __shared__ float sW1[kHid * kIn], sb1[kHid], sW2[kHid * kW2Pitch], sb2[kHid], sW3[kHid], sb3[1];
+    load_weights_q(wt, sW1, sb1, sW2, sb2, sW3, sb3);
     __syncthreads();
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long s = g >> 1;
-    const int hf = (int)(g & 1);
-    const bool ok = s < n;                     // both lanes of a pair agree
+    const long long s = g / kLanes;
+    const int q = (int)(g % kLanes);
+    const bool ok = s < n;                     // the four lanes of a quad agree
     const long long sc = ok ? s : 0;
     float xn[kIn];
 #pragma unroll
     for (int i = 0; i < kIn; i++) xn[i] = (x[sc * kIn + i] - nm.mean[i]) * nm.inv_std[i];
-    // first layer: this lane's half of the outputs, then the partner's half by DPP
-    constexpr int KH = kHid / 2;
-    float mine[KH], h1[kHid];
+    float mine[kQ], h1[kHid];
 #pragma unroll
-    for (int jj = 0; jj < KH; jj++) {
-        const int j = KH * hf + jj;
+    for (int jj = 0; jj < kQ; jj++) {
+        const int j = kQ * q + jj;
         float z = sb1[j];
 #pragma unroll
-        for (int i = 0; i < kIn; i++) z = fmaf(sW1[j * kIn + i], xn[i], z);
+        for (int i = 0; i < kIn; i++) z = fmaf(sW1[(jj * kLanes + q) * kIn + i], xn[i], z);
         if (z1o && ok) z1o[(long long)j * n + s] = z;
         mine[jj] = gelu(z);
     }
 #pragma unroll
-    for (int jj = 0; jj < KH; jj++) {
-        const float other = pair_swap(mine[jj]);
-        h1[jj] = hf ? other : mine[jj];
-        h1[KH + jj] = hf ? mine[jj] : other;
+    for (int jj = 0; jj < kQ; jj++) {
+        const float v[4] = {mine[jj], quad_from<1>(mine[jj]), quad_from<2>(mine[jj]), quad_from<3>(mine[jj])};
+        // quarter Q comes from lane q ^ Q, i.e. v[q ^ Q]
+#pragma unroll
+        for (int Q = 0; Q < kLanes; Q++) {
+            const int m = q ^ Q;
+            h1[kQ * Q + jj] = m == 0 ? v[0] : m == 1 ? v[1] : m == 2 ? v[2] : v[3];
+        }
     }
     float part = 0.0f;
-    for (int kk = 0; kk < kHid / 2; kk++) {
-        const int k = (kHid / 2) * hf + kk;
+    for (int kk = 0; kk < kQ; kk++) {
+        const int k = kQ * q + kk;
         float z = sb2[k];
 #pragma unroll
-        for (int j = 0; j < kHid; j++) z = fmaf(sW2[k * kHid + j], h1[j], z);
+        for (int j = 0; j < kHid; j++) z = fmaf(sW2[(kk * kLanes + q) * kW2Pitch + j], h1[j], z);
         if (z2o && ok) z2o[(long long)k * n + s] = z;
         part = fmaf(sW3[k], gelu(z), part);
     }
-    const float other = pair_swap(part);
-    if (ok && hf == 0) y[s] = sb3[0] + (part + other);
+    const float tot = quad_sum(part, q);
+    if (ok && q == 0) y[s] = sb3[0] + tot;
 }
 
-// Two lanes per sample: the lane of half hf owns dz2 for k in 32 hf .. 32 hf + 31, forms its
-// share of W2^T dz2 for every j, and the pair adds the shares (half 0's first); each lane then
-// writes dz1 for its half of j.
+// Four lanes per sample: the lane of quarter q owns dz2 for k in 16 q .. 16 q + 15, forms its
+// share of W2^T dz2 for every j, and the quad adds the shares in a fixed order; each lane then
+// writes dz1 (and the activations) for its quarter of j.
 __global__ void __launch_bounds__(256)
 k_mlp_bwd_data(Weights wt, const float *__restrict__ z1, const float *__restrict__ z2,
                const float *__restrict__ dy, long long n, float *__restrict__ dz1o,
                float *__restrict__ dz2o, float *__restrict__ h1o, float *__restrict__ h2o)
 {
-    __shared__ float sW1[kHid * kIn], sb1[kHid], sW2[kHid * kHid], sb2[kHid], sW3[kHid], sb3[1];
-    load_weights(wt, sW1, sb1, sW2, sb2, sW3, sb3);
+    __shared__ float sW1[kHid * kIn], sb1[kHid], sW2[kHid * kW2Pitch], sb2[kHid], sW3[kHid], sb3[1];
+    load_weights_q(wt, sW1, sb1, sW2, sb2, sW3, sb3);
     __syncthreads();
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long s = g >> 1;
-    const int hf = (int)(g & 1);
+    const long long s = g / kLanes;
+    const int q = (int)(g % kLanes);
     const bool ok = s < n;
     const long long sc = ok ? s : 0;
     const float gy = dy[sc];
-    constexpr int KH = kHid / 2;
-    float dz2[KH];
+    float dz2[kQ];
 #pragma unroll
-    for (int kk = 0; kk < KH; kk++) {
-        const int k = KH * hf + kk;
-        float g, d;
-        gelu_and_grad(z2[(long long)k * n + sc], g, d);
+    for (int kk = 0; kk < kQ; kk++) {
+        const int k = kQ * q + kk;
+        float gg, d;
+        gelu_and_grad(z2[(long long)k * n + sc], gg, d);
         dz2[kk] = gy * sW3[k] * d;
         if (ok) {
             dz2o[(long long)k * n + s] = dz2[kk];
-            h2o[(long long)k * n + s] = g;
+            h2o[(long long)k * n + s] = gg;
         }
     }
     for (int j = 0; j < kHid; j++) {
         float a = 0.0f;
 #pragma unroll
-        for (int kk = 0; kk < KH; kk++) a = fmaf(sW2[(KH * hf + kk) * kHid + j], dz2[kk], a);
-        const float o = pair_swap(a);
-        const float tot = hf == 0 ? a + o : o + a;
-        if (ok && (j >> 5) == hf) {
-            float g, d;
-            gelu_and_grad(z1[(long long)j * n + s], g, d);
+        for (int kk = 0; kk < kQ; kk++) a = fmaf(sW2[(kk * kLanes + q) * kW2Pitch + j], dz2[kk], a);
+        const float tot = quad_sum(a, q);
+        if (ok && (j / kQ) == q) {
+            float gg, d;
+            gelu_and_grad(z1[(long long)j * n + s], gg, d);
             dz1o[(long long)j * n + s] = tot * d;
-            h1o[(long long)j * n + s] = g;
+            h1o[(long long)j * n + s] = gg;
         }
     }
 }
@@ -274,7 +296,7 @@ struct Grads {
 // The partials are summed in two fixed-order passes, one thread per gradient entry (lanes read
 // consecutive entries of a partial, so loads are coalesced): pass 1 sums groups of kGroup
 // consecutive partials, pass 2 the group sums in order.  The result repeats exactly.
-constexpr int kGroup = 16;
+constexpr int kGroup = 32;
 
 __global__ void __launch_bounds__(256)
 k_mlp_reduce_groups(const float *__restrict__ partial, int n_part, float *__restrict__ grp)
@@ -283,6 +305,7 @@ k_mlp_reduce_groups(const float *__restrict__ partial, int n_part, float *__rest
     if (e >= kEntries) return;
     const int p1 = min(n_part, (g + 1) * kGroup);
     float a = 0.0f;
+#pragma unroll 8
     for (int p = g * kGroup; p < p1; p++) a += partial[(long long)p * kEntries + e];
     grp[(long long)g * kEntries + e] = a;
 }
@@ -293,6 +316,7 @@ k_mlp_reduce(const float *__restrict__ grp, int n_grp, Grads g)
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kEntries) return;
     float a = 0.0f;
+#pragma unroll 8
     for (int q = 0; q < n_grp; q++) a += grp[(long long)q * kEntries + e];
     int o = e;
     if (o < kHid * kIn) { g.w1[o] = a; return; }
@@ -353,8 +377,8 @@ hipError_t launch_mlp_forward(const trs_mlp &m, const trs_mlp_norm &nm, const fl
                               float *y, float *z1, float *z2, hipStream_t s)
 {
     const Weights w{m.w1, m.b1, m.w2, m.b2, m.w3, m.b3};
-    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, w, nm, x, n, y,
-                       z1, z2);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((kLanes * n + 255) / 256)), dim3(256), 0, s, w, nm, x, n,
+                       y, z1, z2);
     return hipGetLastError();
 }
 
@@ -386,8 +410,8 @@ hipError_t launch_mlp_backward(const trs_mlp &m, const trs_mlp_norm &nm, const f
     const long long chunk = mlp_chunk(n);
     const int parts = (int)((n + chunk - 1) / chunk), groups = (parts + kGroup - 1) / kGroup;
     float *grp = part + (long long)parts * kEntries;
-    hipLaunchKernelGGL(k_mlp_bwd_data, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, w, z1, z2,
-                       dy, n, dz1, dz2, h1, h2);
+    hipLaunchKernelGGL(k_mlp_bwd_data, dim3((unsigned)((kLanes * n + 255) / 256)), dim3(256), 0, s, w, z1,
+                       z2, dy, n, dz1, dz2, h1, h2);
     hipLaunchKernelGGL(k_mlp_bwd_w, dim3(parts), dim3(256), 0, s, nm, x, h1, h2, dz1, dz2, dy, n,
                        (int)chunk, part);
     const Grads gg{g.w1, g.b1, g.w2, g.b2, g.w3, g.b3};
