@@ -104,3 +104,42 @@ def test_literal_search_ctu64_matches_oracle(orc):
     ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], f["s2"], cs=cs)
     got = gpu_literal(B.make_frame(w, h, ctu_size=cs), p, cost, f["s1"], f["s2"])
     assert_same_result(got, ref, "1080p CTU 64")
+
+
+def test_literal_search_replays_in_a_graph(orc):
+    """The literal search allocates nothing and clears nothing with memset, so it can be captured;
+    every replay (with eager searches of other frames on the same workspace in between) equals
+    the eager result and the oracle."""
+    import numpy as np
+    import torch
+    w, h = 1280, 768
+    frames = [_inputs(orc, w, h, sd) for sd in (21, 22)]
+    p = B.make_params(8, 4, 3, 4, lam=(1, 10), dtile=-1, drs=-1)
+    fr = B.make_frame(w, h)
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt)).cuda()
+    ins = [(dev(np.asarray(c, np.uint32), np.int32), dev(np.asarray(f["s1"], np.uint32), np.int32),
+            dev(np.asarray(f["s2"], np.uint64), np.int64)) for _, f, c in frames]
+    ws = torch.empty(B.trs_literal_workspace(fr, p), dtype=torch.uint8, device="cuda")
+    out = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    other = torch.empty(B.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    B.trs_literal_search(fr, p, *ins[0], ws, out)
+    torch.cuda.synchronize()
+    eager = out.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            B.trs_literal_search(fr, p, *ins[0], ws, out)
+    torch.cuda.current_stream().wait_stream(s)
+    ref = orc.literal_search(w, h, oracle_params(orc, p), frames[0][2], frames[0][1]["s1"], frames[0][1]["s2"])
+    ref1 = orc.literal_search(w, h, oracle_params(orc, p), frames[1][2], frames[1][1]["s1"], frames[1][1]["s2"])
+    for rep in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {rep}"
+        assert_same_result(B.read_result(out), ref, f"replay {rep}")
+        B.trs_literal_search(fr, p, *ins[1], ws, other)       # eager work on the same workspace
+        torch.cuda.synchronize()
+        assert_same_result(B.read_result(other), ref1, f"eager between replays {rep}")
