@@ -104,7 +104,12 @@ typedef struct trs_blend {
  *                   fewer tiles than cores lower the coding loss); T~(P) is still the slowest
  *                   RS (Eq. 1).  A shape (c, r) is valid when c r <= N and min_rs <= Kmax c r;
  *                   the canonical order is unchanged, over tile choices whose k sum to any n
- *                   in [min_rs, N]. */
+ *                   in [min_rs, N];
+ *   span_tiles      1: besides runs of CTU rows inside one tile, an RS may be a block of two or
+ *                   more complete tiles stacked in one tile column (Section 2.3 allows an RS of
+ *                   several complete tiles forming a rectangle; blocks across tile columns are
+ *                   not covered).  Only trs_literal_search takes it (TRS_ENOTIMPL elsewhere);
+ *                   0 (default) keeps every RS inside one tile. */
 #define TRS_PRUNE_HEIGHTS 1
 #define TRS_PRUNE_MEANS 2
 typedef struct trs_search_params {
@@ -114,6 +119,7 @@ typedef struct trs_search_params {
     int32_t sched_block, sched_item;
     int32_t prune;
     int32_t min_rs;
+    int32_t span_tiles;
     int64_t space_budget;
 } trs_search_params;
 

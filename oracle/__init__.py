@@ -30,7 +30,7 @@ class OrcParams(ctypes.Structure):
                 ("area_k", ctypes.c_int32), ("lambda_num", ctypes.c_int32),
                 ("lambda_den", ctypes.c_int32), ("dtile", ctypes.c_int32),
                 ("drs", ctypes.c_int32), ("prune", ctypes.c_int32), ("min_rs", ctypes.c_int32),
-                ("space_budget", ctypes.c_int64)]
+                ("span_tiles", ctypes.c_int32), ("space_budget", ctypes.c_int64)]
 
 
 class OrcResult(ctypes.Structure):
@@ -110,10 +110,10 @@ def cost_map(tex: np.ndarray, prev: np.ndarray | None, a: int = 200, b: int = 3,
 
 def make_params(n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile, area_k=3,
                 lam=(0, 1), dtile=-2, drs=-2, space_budget=1 << 24, prune=0,
-                min_rs=0) -> OrcParams:
+                min_rs=0, span_tiles=0) -> OrcParams:
     num, den = lam
     return OrcParams(n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile, area_k,
-                     num, den, dtile, drs, prune, min_rs, space_budget)
+                     num, den, dtile, drs, prune, min_rs, span_tiles, space_budget)
 
 
 def space_size(W: int, H: int, params: OrcParams) -> tuple[int, int, int]:

@@ -161,3 +161,96 @@ def brute_search(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3,
     best = min(pool, key=lambda s: (s[3], s[2], s[0]))
     out.update(rank=best[0], t_min=tmin, t_sel=best[2], q_sel=best[3], rs=best[4])
     return out
+
+
+def enumerate_spanning(W, H, N, Cmax, Rmax, Kmax):
+    """The literal space in which an RS may also be a block of two or more complete tiles stacked
+    in one tile column: every (c, r, X, Y) and, per tile column, every way to cover its r tiles
+    from top to bottom with single tiles cut into k slices (any split rows) or blocks of >= 2
+    tiles; N RS in all.  Each candidate is (c, r, X, Y, columns), a column being a tuple of
+    ('t', j, k, Z) and ('b', a, b) items."""
+    def coverings(yb, j, r):
+        if j == r:
+            yield ()
+            return
+        hj = yb[j + 1] - yb[j]
+        for k in range(1, min(Kmax, hj) + 1):
+            for Z in boundary_vectors(hj, k, None):
+                for rest in coverings(yb, j + 1, r):
+                    yield (('t', j, k, Z),) + rest
+        for b in range(j + 2, r + 1):
+            for rest in coverings(yb, b, r):
+                yield (('b', j, b),) + rest
+
+    def count_rs(col):
+        return sum(it[2] if it[0] == 't' else 1 for it in col)
+
+    out = []
+    for c in range(1, Cmax + 1):
+        for r in range(1, Rmax + 1):
+            for X in boundary_vectors(W, c, None):
+                for Y in boundary_vectors(H, r, None):
+                    yb = (0,) + Y + (H,)
+                    cols = [(col, count_rs(col)) for col in coverings(yb, 0, r)]
+                    for choice in itertools.product(cols, repeat=c):
+                        if sum(n for _, n in choice) == N:
+                            out.append((c, r, X, Y, tuple(col for col, _ in choice)))
+    return out
+
+
+def spanning_regions(W, H, cand):
+    """RS rectangles of a spanning candidate, tiles in raster order: a block is listed at its top
+    tile, a cut tile lists its slices top to bottom."""
+    c, r, X, Y, cols = cand
+    xb = (0,) + X + (W,)
+    yb = (0,) + Y + (H,)
+    at = {}
+    for i, col in enumerate(cols):
+        for it in col:
+            at[(it[1], i)] = it
+    rs = []
+    for j in range(r):
+        for i in range(c):
+            it = at.get((j, i))
+            if it is None:
+                continue
+            if it[0] == 'b':
+                rs.append((xb[i], yb[it[1]], xb[i + 1], yb[it[2]]))
+            else:
+                _, _, k, Z = it
+                zb = (0,) + Z + (yb[j + 1] - yb[j],)
+                for q in range(k):
+                    rs.append((xb[i], yb[j] + zb[q], xb[i + 1], yb[j] + zb[q + 1]))
+    return rs
+
+
+def brute_spanning(luma, cost, cs, N, Cmax, Rmax, Kmax, lam=Fraction(0), area_k=3):
+    """Two-step search over enumerate_spanning's candidates with direct sums (as brute_search)."""
+    h, w = luma.shape
+    W, H = (w + cs - 1) // cs, (h + cs - 1) // cs
+    n, s1, s2, _ = ctu_stats_pixels(luma, cs)
+    T = [[int(cost[y * W + x]) for x in range(W)] for y in range(H)]
+    cands = enumerate_spanning(W, H, N, Cmax, Rmax, Kmax)
+
+    def rsum(a, rect):
+        x0, y0, x1, y1 = rect
+        return sum(a[y][x] for y in range(y0, y1) for x in range(x0, x1))
+
+    scored = []
+    for rank, cand in enumerate(cands):
+        rs = spanning_regions(W, H, cand)
+        areas = [rsum(n, q) for q in rs]
+        feasible = area_k == 0 or area_k * min(areas) > max(areas)
+        t = max(rsum(T, q) for q in rs)
+        qv = sum(rsum(s2, q) - (rsum(s1, q) ** 2) // rsum(n, q) for q in rs)
+        scored.append((rank, feasible, t, qv, rs))
+    feas = [s for s in scored if s[1]]
+    out = dict(n_enumerated=len(cands), n_feasible=len(feas))
+    if not feas:
+        out.update(rank=None)
+        return out
+    tmin = min(s[2] for s in feas)
+    pool = feas if lam is None else [s for s in feas if s[2] <= tmin * (1 + lam)]
+    best = min(pool, key=lambda s: (s[3], s[2], s[0]))
+    out.update(rank=best[0], t_min=tmin, t_sel=best[2], q_sel=best[3], rs=best[4])
+    return out

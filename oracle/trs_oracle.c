@@ -61,6 +61,7 @@ typedef struct {
     int32_t lambda_num, lambda_den, dtile, drs;
     int32_t prune;          /* bit 0: slice heights within 2x in a tile; bit 1: tile mean areas */
     int32_t min_rs;         /* RS counts n in [min_rs, N] (idle threads); 0 means N */
+    int32_t span_tiles;     /* 1: an RS may be a block of complete tiles stacked in one tile column */
     int64_t space_budget;
 } orc_params;
 
@@ -685,7 +686,7 @@ typedef struct { int64_t q, t; } lexv;          /* (Q, T~) of step 2; q = INT64_
 static const int64_t LIT_INF = INT64_MAX;
 
 typedef struct {
-    int W, H, N, Cm, Rm, Km;
+    int W, H, N, Cm, Rm, Km, span;
     int64_t *colpx, *rowpx, *satT, *satS1, *satS2;
     /* per rectangle (x0, x1, y0, y1): area, time, q = S2 - floor(S1^2 / n) */
     int64_t *A, *T, *Q;
@@ -773,7 +774,11 @@ static void lit_tables(lit_ctx *L, int step)
 }
 
 /* Best RS count split over the r tiles of column strip [x0, x1) with rows Y: out[K] for K
- * slices in the strip (K = 0..N); kk (optional) receives the per-tile counts for K = want. */
+ * slices in the strip (K = 0..N).  Each tile takes k slices of its own, or (span_tiles) two or
+ * more consecutive tiles form one RS; ch[b][K] records the choice that ends at tile row b: k > 0
+ * for tile b - 1 cut into k slices, -(a + 1) for the block of tiles a .. b - 1.  Single tiles
+ * are tried first (k ascending), then blocks (a ascending); the first minimum is kept.  kk
+ * (optional) receives the choices of the best split with K = want, listed by ending row. */
 static void lit_strip(const lit_ctx *L, int step, int x0, int x1, int r, const int *Y,
                       int64_t *o1, lexv *o2, int want, int *kk)
 {
@@ -784,21 +789,37 @@ static void lit_strip(const lit_ctx *L, int step, int x0, int x1, int r, const i
     for (int K = 0; K <= N; K++) { u1[0][K] = LIT_INF; u2[0][K].q = LIT_INF; u2[0][K].t = LIT_INF; }
     u1[0][0] = 0;
     u2[0][0].q = 0; u2[0][0].t = 0;
-    for (int j = 0; j < r; j++) {
-        size_t base = lit_rect(L, x0, x1, Y[j], Y[j + 1]) * (size_t)Km;
+    for (int b = 1; b <= r; b++) {
+        size_t base = lit_rect(L, x0, x1, Y[b - 1], Y[b]) * (size_t)Km;
         for (int K = 0; K <= N; K++) {
-            u1[j + 1][K] = LIT_INF;
-            u2[j + 1][K].q = LIT_INF; u2[j + 1][K].t = LIT_INF;
-            ch[j + 1][K] = 0;
+            u1[b][K] = LIT_INF;
+            u2[b][K].q = LIT_INF; u2[b][K].t = LIT_INF;
+            ch[b][K] = 0;
             for (int k = 1; k <= Km && k <= K; k++) {
                 if (step == 1) {
-                    int64_t a = u1[j][K - k], b = L->t1[base + k - 1];
-                    if (a == LIT_INF || b == LIT_INF) continue;
-                    int64_t v = a > b ? a : b;
-                    if (v < u1[j + 1][K]) { u1[j + 1][K] = v; ch[j + 1][K] = k; }
+                    int64_t a = u1[b - 1][K - k], c = L->t1[base + k - 1];
+                    if (a == LIT_INF || c == LIT_INF) continue;
+                    int64_t v = a > c ? a : c;
+                    if (v < u1[b][K]) { u1[b][K] = v; ch[b][K] = k; }
                 } else {
-                    lexv v = lex_join(u2[j][K - k], L->t2[base + k - 1]);
-                    if (v.q != LIT_INF && lex_less(v, u2[j + 1][K])) { u2[j + 1][K] = v; ch[j + 1][K] = k; }
+                    lexv v = lex_join(u2[b - 1][K - k], L->t2[base + k - 1]);
+                    if (v.q != LIT_INF && lex_less(v, u2[b][K])) { u2[b][K] = v; ch[b][K] = k; }
+                }
+            }
+            if (!L->span || K < 1) continue;
+            for (int a = 0; a + 2 <= b; a++) {               /* block of tiles a .. b - 1: one RS */
+                size_t rr = lit_rect(L, x0, x1, Y[a], Y[b]);
+                if (!lit_ok(L, rr)) continue;
+                if (step == 1) {
+                    int64_t av = u1[a][K - 1];
+                    if (av == LIT_INF) continue;
+                    int64_t v = av > L->T[rr] ? av : L->T[rr];
+                    if (v < u1[b][K]) { u1[b][K] = v; ch[b][K] = -(a + 1); }
+                } else {
+                    if (L->T[rr] > L->tau) continue;
+                    lexv blk = { L->Q[rr], L->T[rr] };
+                    lexv v = lex_join(u2[a][K - 1], blk);
+                    if (v.q != LIT_INF && lex_less(v, u2[b][K])) { u2[b][K] = v; ch[b][K] = -(a + 1); }
                 }
             }
         }
@@ -807,8 +828,15 @@ static void lit_strip(const lit_ctx *L, int step, int x0, int x1, int r, const i
         if (o1) o1[K] = u1[r][K];
         if (o2) o2[K] = u2[r][K];
     }
-    if (kk)
-        for (int j = r, K = want; j > 0; j--) { kk[j - 1] = ch[j][K]; K -= ch[j][K]; }
+    if (kk) {
+        for (int b = 0; b <= r; b++) kk[b] = 0;
+        for (int b = r, K = want; b > 0;) {
+            const int c = ch[b][K];
+            kk[b] = c;
+            if (c > 0) { K -= c; b -= 1; }
+            else { K -= 1; b = -c - 1; }
+        }
+    }
 }
 
 /* Column DP for fixed window and Y.  best1[c] / best2[c]: best over c tile columns (c = 1..Cm).
@@ -889,6 +917,49 @@ static int cmp_i64(const void *a, const void *b)
     return x < y ? -1 : x > y;
 }
 
+/* |C| of the literal space with spanning blocks: per shape, |X| times the sum over Y of the
+ * coefficient of z^N in S_Y(z)^c, where S_Y(z) counts the ways to cover one tile column with
+ * rows Y: tile rows one at a time (a tile of height h split into k slices: the number of split
+ * vectors) or two or more consecutive tile rows as one RS (z).  Saturating. */
+static int64_t span_space_size(int W, int H, const orc_params *p)
+{
+    const int N = p->n_threads, Km = p->max_rs_per_tile;
+    uint64_t total = 0;
+    for (int r = 1; r <= p->max_tile_rows && r <= H; r++) {
+        vec_list ys = gen_vectors(r, H, -1);
+        for (int64_t yi = 0; yi < ys.n; yi++) {
+            const int *Y = ys.v + yi * (r + 1);
+            uint64_t f[ORC_MAXB][ORC_MAXN + 1];
+            memset(f, 0, sizeof(f));
+            f[0][0] = 1;
+            for (int b = 1; b <= r; b++) {
+                const int hb = Y[b] - Y[b - 1];
+                for (int n = 0; n <= N; n++) {
+                    uint64_t acc = 0;
+                    for (int k = 1; k <= Km && k <= hb && k <= n; k++)
+                        acc = sat_add(acc, sat_mul(f[b - 1][n - k], count_vectors(k, hb, -1)));
+                    for (int a = 0; a + 2 <= b && n >= 1; a++) acc = sat_add(acc, f[a][n - 1]);
+                    f[b][n] = acc;
+                }
+            }
+            uint64_t poly[ORC_MAXN + 1] = {0};
+            poly[0] = 1;
+            for (int c = 1; c <= p->max_tile_cols && c <= W; c++) {
+                uint64_t q[ORC_MAXN + 1] = {0};
+                for (int a = 0; a <= N; a++) {
+                    if (!poly[a]) continue;
+                    for (int b2 = 0; a + b2 <= N; b2++)
+                        if (f[r][b2]) q[a + b2] = sat_add(q[a + b2], sat_mul(poly[a], f[r][b2]));
+                }
+                memcpy(poly, q, sizeof(q));
+                total = sat_add(total, sat_mul(count_vectors(c, W, -1), poly[N]));
+            }
+        }
+        free(ys.v);
+    }
+    return total > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)total;
+}
+
 int orc_literal_search(int w, int h, int cs, const orc_params *p, const uint32_t *cost,
                        const uint32_t *s1, const uint64_t *s2, orc_result *out)
 {
@@ -897,11 +968,12 @@ int orc_literal_search(int w, int h, int cs, const orc_params *p, const uint32_t
     const int W = (w + cs - 1) / cs, H = (h + cs - 1) / cs;
     if (W > 64 || H > 64 || p->n_threads < 1 || p->n_threads > ORC_MAXN || p->max_tile_cols < 1 ||
         p->max_tile_rows < 1 || p->max_rs_per_tile < 1 || p->lambda_den < 1 || p->area_k < 0 ||
-        p->prune != 0 || (p->min_rs != 0 && p->min_rs != p->n_threads))
+        p->prune != 0 || (p->min_rs != 0 && p->min_rs != p->n_threads) || p->span_tiles < 0 ||
+        p->span_tiles > 1)
         return -1;
     lit_ctx L;
     memset(&L, 0, sizeof(L));
-    L.W = W; L.H = H; L.N = p->n_threads;
+    L.W = W; L.H = H; L.N = p->n_threads; L.span = p->span_tiles;
     L.Cm = p->max_tile_cols < W ? p->max_tile_cols : W;
     L.Rm = p->max_tile_rows < H ? p->max_tile_rows : H;
     L.Km = p->max_rs_per_tile < H ? p->max_rs_per_tile : H;
@@ -964,6 +1036,7 @@ int orc_literal_search(int w, int h, int cs, const orc_params *p, const uint32_t
     orc_params lp = *p;
     lp.dtile = -1; lp.drs = -1;
     orc_space_size(W, H, &lp, &cnt, &dtu, &dru);
+    if (p->span_tiles) cnt = span_space_size(W, H, p);
     out->n_enumerated = cnt;
     out->n_feasible = -1;
     out->rank = -1;
@@ -1055,11 +1128,17 @@ int orc_literal_search(int w, int h, int cs, const orc_params *p, const uint32_t
         lit_tables(&L, 2);
         int cx[ORC_MAXB], ck[ORC_MAXB];
         lit_columns(&L, 2, br, bY, NULL, b2, bc, cx, ck);
-        int tk[ORC_MAXB][ORC_MAXB];                   /* [column][row] slice counts */
+        /* per tile: its slice count, or -(b + 1) on the top tile of a block ending at row b,
+           or 0 inside a block */
+        int tk[ORC_MAXB][ORC_MAXB];
         for (int i = 0; i < bc; i++) {
-            int kk[ORC_MAXB];
+            int kk[ORC_MAXB + 1];
             lit_strip(&L, 2, cx[i], cx[i + 1], br, bY, NULL, NULL, ck[i], kk);
-            for (int j = 0; j < br; j++) tk[i][j] = kk[j];
+            for (int j = 0; j < br; j++) tk[i][j] = 0;
+            for (int b = 1; b <= br; b++) {
+                if (kk[b] > 0) tk[i][b - 1] = kk[b];
+                else if (kk[b] < 0) tk[i][-kk[b] - 1] = -(b + 1);
+            }
         }
         int64_t (*f1)[ORC_MAXB] = malloc(sizeof(int64_t) * ORC_MAXB * ORC_MAXB);
         lexv (*f2)[ORC_MAXB] = malloc(sizeof(lexv) * ORC_MAXB * ORC_MAXB);
@@ -1068,6 +1147,18 @@ int orc_literal_search(int w, int h, int cs, const orc_params *p, const uint32_t
         int64_t tsel = 0, qsel = 0;
         for (int j = 0; j < br; j++)
             for (int i = 0; i < bc; i++) {
+                if (tk[i][j] < 0) {                   /* a block of tiles j .. b - 1 as one RS */
+                    const int b = -tk[i][j] - 1;
+                    size_t rr = lit_rect(&L, cx[i], cx[i + 1], bY[j], bY[b]);
+                    out->rs[n][0] = cx[i]; out->rs[n][1] = bY[j];
+                    out->rs[n][2] = cx[i + 1]; out->rs[n][3] = bY[b];
+                    out->rs_time[n] = L.T[rr];
+                    if (L.T[rr] > tsel) tsel = L.T[rr];
+                    qsel += L.Q[rr];
+                    n++;
+                    continue;
+                }
+                if (tk[i][j] == 0) continue;          /* inside a block */
                 lit_tile_dp(&L, 2, cx[i], cx[i + 1], bY[j], f1, f2, arg);
                 int rows[ORC_MAXB], kq = tk[i][j];
                 rows[kq] = bY[j + 1];

@@ -40,7 +40,7 @@ class SearchParams(ctypes.Structure):
                 ("lambda_den", ctypes.c_int32), ("dtile", ctypes.c_int32), ("drs", ctypes.c_int32),
                 ("sched_block", ctypes.c_int32), ("sched_item", ctypes.c_int32),
                 ("prune", ctypes.c_int32), ("min_rs", ctypes.c_int32),
-                ("space_budget", ctypes.c_int64)]
+                ("span_tiles", ctypes.c_int32), ("space_budget", ctypes.c_int64)]
 
 
 class PlanStats(ctypes.Structure):
@@ -198,11 +198,11 @@ def make_frame(width: int, height: int, ctu_size: int = 128, bit_depth: int = 10
 def make_params(n_threads: int, max_tile_cols: int, max_tile_rows: int, max_rs_per_tile: int,
                 area_k: int = 3, lam=(0, 1), dtile: int = -2, drs: int = -2,
                 sched_block: int = 0, sched_item: int = 0, space_budget: int = 1 << 24,
-                prune: int = 0, min_rs: int = 0) -> SearchParams:
+                prune: int = 0, min_rs: int = 0, span_tiles: int = 0) -> SearchParams:
     num, den = lam
     return SearchParams(n_threads, max_tile_cols, max_tile_rows, max_rs_per_tile, area_k,
                         num, den, dtile, drs, sched_block, sched_item, prune, min_rs,
-                        space_budget)
+                        span_tiles, space_budget)
 
 
 # ---- host-only calls ---------------------------------------------------------------------

@@ -173,6 +173,7 @@ trs_status check_space_args(const trs_frame *f, const trs_search_params *p)
     if (p->area_k < 0 || p->area_k > 1000000) return TRS_EINVAL;
     if (p->prune < 0 || p->prune > 3) return TRS_EINVAL;
     if (p->min_rs < 0 || p->min_rs > p->n_threads) return TRS_EINVAL;
+    if (p->span_tiles < 0 || p->span_tiles > 1) return TRS_EINVAL;
     if (p->lambda_den < 1 || p->lambda_den > 65535 || p->lambda_num > 65535) return TRS_EINVAL;
     bool ladder = p->dtile == -2 && p->drs == -2;
     if (!ladder && (p->dtile < -1 || p->drs < -1)) return TRS_EINVAL;
@@ -185,6 +186,7 @@ trs_status check_space_args(const trs_frame *f, const trs_search_params *p)
 trs_status space_size(int W, int H, const trs_search_params *p, int64_t *n, int32_t *dt, int32_t *dr)
 {
     if (W < 1 || H < 1 || W > kMaxGrid || H > kMaxGrid) return TRS_EINVAL;
+    if (p->span_tiles) return TRS_ENOTIMPL;          // only the literal-space search covers blocks
     int a, b;
     if (p->dtile == -2 && p->drs == -2) {
         u64 budget = p->space_budget > 0 ? (u64)p->space_budget : (u64(1) << 24);

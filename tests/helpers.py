@@ -75,7 +75,7 @@ def gpu_literal(frame, params, cost: np.ndarray, s1: np.ndarray, s2: np.ndarray)
 def oracle_params(orc, p: "B.SearchParams"):
     return orc.make_params(p.n_threads, p.max_tile_cols, p.max_tile_rows, p.max_rs_per_tile,
                            p.area_k, (p.lambda_num, p.lambda_den), p.dtile, p.drs, p.space_budget, p.prune,
-                           p.min_rs)
+                           p.min_rs, p.span_tiles)
 
 
 def assert_same_result(gpu: dict, ref: dict, ctx: str = ""):

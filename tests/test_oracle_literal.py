@@ -119,3 +119,43 @@ def test_rejects_what_it_does_not_cover(orc):
         p = orc.make_params(3, 3, 3, 2, dtile=-1, drs=-1, **kw)
         with pytest.raises(ValueError):
             orc.literal_search(640, 512, p, cost, f["s1"], f["s2"])
+
+
+@pytest.mark.parametrize("w,h,N,C,R,K,seed", [(384, 512, 3, 2, 3, 2, 0), (512, 640, 4, 3, 3, 2, 1),
+                                              (640, 512, 3, 3, 2, 2, 2), (384, 768, 4, 2, 4, 2, 3),
+                                              (512, 512, 2, 2, 3, 2, 4)])
+@pytest.mark.parametrize("lam", [(0, 1), (1, 10), (-1, 1)])
+@pytest.mark.parametrize("area_k", [3, 0])
+def test_spanning_blocks_match_brute_force(orc, w, h, N, C, R, K, seed, lam, area_k):
+    """RS that may also be blocks of complete tiles stacked in one tile column: the oracle's DP
+    (blocks as one more choice in the strip DP) against the brute force, which lists every
+    covering of every tile column; the count of the space is checked against the list."""
+    from fractions import Fraction
+
+    from oracle import brute
+    luma, f, cost = _inputs(orc, w, h, seed)
+    p = orc.make_params(N, C, R, K, area_k=area_k, lam=lam, dtile=-1, drs=-1, span_tiles=1)
+    d = orc.literal_search(w, h, p, cost, f["s1"], f["s2"])
+    b = brute.brute_spanning(luma, cost, 128, N, C, R, K, lam=None if lam[0] < 0 else Fraction(*lam),
+                             area_k=area_k)
+    assert d["n_enumerated"] == b["n_enumerated"]
+    if b["rank"] is None:
+        assert d["status"] == 1
+        return
+    assert (d["t_min"], d["t_sel"], d["q_sel"]) == (b["t_min"], b["t_sel"], b["q_sel"])
+    assert sorted(d["rs"]) == sorted(b["rs"])
+    assert d["n_rs"] == N
+
+
+def test_spanning_blocks_widen_the_space(orc):
+    """Blocks only add candidates: T~min cannot rise; on this frame it falls (a tall tile column
+    is one RS while its neighbour is cut at a row boundary the first one does not need)."""
+    w, h = 384, 768
+    luma, f, cost = _inputs(orc, w, h, 3)
+    plain = orc.literal_search(w, h, orc.make_params(4, 2, 4, 2, dtile=-1, drs=-1), cost, f["s1"], f["s2"])
+    span = orc.literal_search(w, h, orc.make_params(4, 2, 4, 2, dtile=-1, drs=-1, span_tiles=1), cost,
+                              f["s1"], f["s2"])
+    assert span["n_enumerated"] > plain["n_enumerated"]
+    assert span["t_min"] < plain["t_min"]
+    bd = span["row_bd"]
+    assert any(any(r[1] < y < r[3] for y in bd) for r in span["rs"])    # an RS across a row boundary
