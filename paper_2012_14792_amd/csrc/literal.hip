@@ -45,12 +45,12 @@ namespace {
 constexpr long long kInf = LLONG_MAX;
 constexpr unsigned long long kNone = ~0ull;
 constexpr int kMaxW = 64, kMaxH = 40, kMaxN = 32;
-constexpr size_t kLdsLimit = 64 * 1024;
+constexpr size_t kLdsLimit = 160 * 1024;    // LDS per work-group on gfx950
 constexpr long long kUnitCap = 1ll << 24;
 
 // Device view of the host tables (by value).
 struct LitView {
-    int W, H, N, Cm, Rm, Km, S, R2, n_win, nY, n_units, karea, lam_num, lam_den, yrow, pad;
+    int W, H, N, Cm, Rm, Km, S, R2, n_win, nY, n_units, karea, lam_num, lam_den, yrow, span;
     long long n_enumerated;
     const int *colpx, *rowpx;           // pixel prefix sums
     const long long *win;               // window lower bounds a (upper bound k a, or none)
@@ -248,9 +248,10 @@ struct UnitLds {
     unsigned char *AX, *AK;
 };
 
-__host__ __device__ inline size_t unit_lds_bytes(int W, int N, int Cm, int Rm, int Km, int step, bool rec)
+__host__ __device__ inline size_t unit_lds_bytes(int W, int N, int Cm, int Rm, int Km, int step, bool rec,
+                                                 int span)
 {
-    const size_t hs = (size_t)W * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    const size_t hs = (size_t)W * (span ? Rm + 1 : 1) * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
     const size_t tv = (size_t)W * Rm * Km;
     size_t b = 8 * (hs + F + tv) * (step == 2 ? 2 : 1) + 4 * ((size_t)W + (size_t)(Cm + 1) * (W + 1));
     if (rec) b += 2 * F;
@@ -258,9 +259,9 @@ __host__ __device__ inline size_t unit_lds_bytes(int W, int N, int Cm, int Rm, i
 }
 
 __device__ inline UnitLds unit_lds(unsigned char *raw, int W, int N, int Cm, int Rm, int Km, int step,
-                                   bool rec)
+                                   bool rec, int span)
 {
-    const size_t hs = (size_t)W * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    const size_t hs = (size_t)W * (span ? Rm + 1 : 1) * (N + 1), F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
     const size_t tv = (size_t)W * Rm * Km;
     UnitLds L{};
     long long *p = reinterpret_cast<long long *>(raw);
@@ -301,7 +302,10 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
     }
     auto fi = [&](int i, int x, int n) { return ((size_t)i * (W + 1) + x) * (N + 1) + n; };
     auto keep = [&](long long t, long long q) { return t <= bt && (STEP == 1 || q <= bq); };
-    const int Rm = v.Rm;
+    const int Rm = v.Rm, RR = v.span ? Rm + 1 : 1;
+    const long long lo = v.win[wi];
+    const long long hi = v.karea ? (long long)v.karea * lo : kInf;
+    const unsigned long long tau = STEP == 2 ? eq4_bound(w.hdr[0], v.lam_num, v.lam_den) : kNone;
     for (int x = 1; x <= W; x++) {
         // tile values (k = 1 .. Km) of the r tiles of every strip [x', x), loaded together
         for (int e = lane; e < x * r; e += blockDim.x) {
@@ -314,36 +318,55 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
             }
         }
         __syncthreads();
-        // strips [x', x): DP over the r tiles, in place in row x' of hs
+        // strips [x', x): DP over the r tile-row levels.  With blocks of tiles allowed every
+        // level has its own row of hs (a block ending at level b starts from a level a <= b - 2);
+        // otherwise one row is updated in place, K descending.  Tiles are tried first (k
+        // ascending), then blocks (a ascending), as in the oracle.
         for (int xp = lane; xp < x; xp += blockDim.x) {
-            long long *hT = L.hsT + (size_t)xp * (N + 1);
-            long long *hQ = STEP == 2 ? L.hsQ + (size_t)xp * (N + 1) : nullptr;
+            long long *baseT = L.hsT + (size_t)xp * RR * (N + 1);
+            long long *baseQ = STEP == 2 ? L.hsQ + (size_t)xp * RR * (N + 1) : nullptr;
+            auto rowT = [&](int b) { return baseT + (size_t)(v.span ? b : 0) * (N + 1); };
+            auto rowQ = [&](int b) { return baseQ + (size_t)(v.span ? b : 0) * (N + 1); };
             for (int K = 0; K <= N; K++) {
-                hT[K] = K == 0 ? 0 : kInf;
-                if (STEP == 2) hQ[K] = K == 0 ? 0 : kInf;
+                rowT(0)[K] = K == 0 ? 0 : kInf;
+                if (STEP == 2) rowQ(0)[K] = K == 0 ? 0 : kInf;
             }
+            const size_t rs0 = (size_t)sidx(xp, x, W) * R2;
             bool any = true;
-            for (int j = 0; j < r && any; j++) {
-                const long long *tvT = L.tvT + ((size_t)xp * Rm + j) * Km;
-                const long long *tvQ = STEP == 2 ? L.tvQ + ((size_t)xp * Rm + j) * Km : nullptr;
+            for (int b = 1; b <= r && (any || v.span); b++) {
+                const long long *tvT = L.tvT + ((size_t)xp * Rm + (b - 1)) * Km;
+                const long long *tvQ = STEP == 2 ? L.tvQ + ((size_t)xp * Rm + (b - 1)) * Km : nullptr;
+                const long long *sT = rowT(b - 1), *sQ = STEP == 2 ? rowQ(b - 1) : nullptr;
+                long long *dT = rowT(b), *dQ = STEP == 2 ? rowQ(b) : nullptr;
                 any = false;
                 for (int K = N; K >= 0; K--) {
                     long long ct = kInf, cq = kInf;
                     for (int k = 1; k <= Km && k <= K; k++) {
-                        const long long at = hT[K - k], tt = tvT[k - 1];
+                        const long long at = sT[K - k], tt = tvT[k - 1];
                         if (at == kInf || tt == kInf) continue;
                         const long long t = at > tt ? at : tt;
-                        const long long q = STEP == 2 ? hQ[K - k] + tvQ[k - 1] : 0;
+                        const long long q = STEP == 2 ? sQ[K - k] + tvQ[k - 1] : 0;
                         if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; }
                     }
+                    if (v.span && K >= 1)
+                        for (int a = 0; a + 2 <= b; a++) {            // tiles a .. b - 1 as one RS
+                            const size_t ri = rs0 + ridx(Yl[a], Yl[b], v.H);
+                            const long long A = w.rA[ri], bT = w.rT[ri];
+                            if (A < lo || A >= hi || (STEP == 2 && (unsigned long long)bT > tau)) continue;
+                            const long long at = rowT(a)[K - 1];
+                            if (at == kInf) continue;
+                            const long long t = at > bT ? at : bT;
+                            const long long q = STEP == 2 ? rowQ(a)[K - 1] + w.rQ[ri] : 0;
+                            if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; }
+                        }
                     if (ct != kInf && !REC && !keep(ct, cq)) ct = cq = kInf;
-                    hT[K] = ct;
-                    if (STEP == 2) hQ[K] = cq;
+                    dT[K] = ct;
+                    if (STEP == 2) dQ[K] = cq;
                     any |= ct != kInf;
                 }
             }
             if (!any)
-                for (int K = 0; K <= N; K++) hT[K] = kInf;
+                for (int K = 0; K <= N; K++) rowT(v.span ? r : 0)[K] = kInf;
             L.hsOk[xp] = any;
         }
         __syncthreads();
@@ -355,13 +378,14 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
             int ax = -1, ak = -1;
             for (int xp = i - 1; xp < x; xp++) {
                 if (!L.hsOk[xp] || !L.FOk[(i - 1) * (W + 1) + xp]) continue;
-                const long long *hT = L.hsT + (size_t)xp * (N + 1);
+                const size_t hrow = ((size_t)xp * RR + (v.span ? r : 0)) * (N + 1);
+                const long long *hT = L.hsT + hrow;
                 for (int K = 1; K <= n; K++) {
                     const size_t fp = fi(i - 1, xp, n - K);
                     const long long at = L.FT[fp], tt = hT[K];
                     if (at == kInf || tt == kInf) continue;
                     const long long t = at > tt ? at : tt;
-                    const long long q = STEP == 2 ? L.FQ[fp] + L.hsQ[(size_t)xp * (N + 1) + K] : 0;
+                    const long long q = STEP == 2 ? L.FQ[fp] + L.hsQ[hrow + K] : 0;
                     if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; ax = xp; ak = K; }
                 }
             }
@@ -397,11 +421,18 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
     const int W = v.W, N = v.N, Cm = v.Cm, Km = v.Km, S = v.S, R2 = v.R2, Rm = v.Rm, NP = N + 1;
     const int wi = u / v.nY, yi = u % v.nY;
     const size_t F = (size_t)(Cm + 1) * (W + 1) * NP;
+    // strip rows: all r + 1 tile-row levels when blocks of tiles are allowed (a block ending at
+    // level b starts from level a <= b - 2), else two levels used in turn
+    const int RR = v.span ? Rm + 1 : 2, NPR = v.span ? Rm * (Rm - 1) / 2 : 0;
+    auto rowi = [&](int b) { return v.span ? b : (b & 1); };
     V *FT = reinterpret_cast<V *>(raw);
-    V *hsA = FT + F, *hsB = hsA + (size_t)W * NP;
-    V *tv = hsB + (size_t)W * NP;
-    unsigned *FOk = reinterpret_cast<unsigned *>(tv + (size_t)W * Rm * Km);
+    V *hs = FT + F;
+    V *tv = hs + (size_t)W * RR * NP;
+    V *bv = tv + (size_t)W * Rm * Km;                       // block values [x'][pair (a, b)]
+    unsigned *FOk = reinterpret_cast<unsigned *>(bv + (size_t)W * NPR);
     unsigned *hsOk = FOk + (size_t)(Cm + 1) * (W + 1);
+    const long long lo = v.win[wi];
+    const long long hi = v.karea ? (long long)v.karea * lo : kInf;
     const unsigned char *yt = v.ytab + (size_t)yi * v.yrow;
     r = yt[0];
     for (int j = lane; j <= r; j += blockDim.x) Yl[j] = yt[1 + j];
@@ -419,33 +450,47 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
                 tv[lb + k] = narrow(w.tT[tb + k]);
             }
         }
+        const int npair = v.span ? r * (r - 1) / 2 : 0;
+        for (int e = lane; e < x * npair; e += blockDim.x) {
+            const int xp = e / npair;
+            int pr = e - xp * npair, b = 2;
+            while (pr >= b - 1) { pr -= b - 1; b++; }            // pair index (b-2)(b-1)/2 + a
+            const size_t ri = (size_t)sidx(xp, x, W) * R2 + ridx(Yl[pr], Yl[b], v.H);
+            const long long A = w.rA[ri];
+            bv[(size_t)xp * NPR + (e - xp * npair)] = A >= lo && A < hi ? narrow(w.rT[ri]) : kNo;
+        }
         for (int e = lane; e < x * NP; e += blockDim.x) {
             unsigned xp, K;
             divNP.divmod((unsigned)e, xp, K);
-            hsA[e] = K == 0 ? V(0) : kNo;
+            hs[((size_t)xp * RR + rowi(0)) * NP + K] = K == 0 ? V(0) : kNo;
         }
         for (int xp = lane; xp < x; xp += blockDim.x) hsOk[xp] = 0;
         __syncthreads();
-        V *cur = hsA, *nxt = hsB;
-        for (int j = 0; j < r; j++) {
+        for (int b = 1; b <= r; b++) {
             for (int e = lane; e < x * NP; e += blockDim.x) {
                 unsigned xp, K;
                 divNP.divmod((unsigned)e, xp, K);
-                const V *tj = tv + ((size_t)xp * Rm + j) * Km;
-                const V *row = cur + (size_t)xp * NP;
+                const V *tj = tv + ((size_t)xp * Rm + (b - 1)) * Km;
+                const V *row = hs + ((size_t)xp * RR + rowi(b - 1)) * NP;
                 V best = kNo;
                 const int kmax = (int)K < Km ? (int)K : Km;
                 for (int k = 1; k <= kmax; k++) {
-                    const V a = row[K - k], b = tj[k - 1];
-                    const V t = a > b ? a : b;
+                    const V a = row[K - k], c = tj[k - 1];
+                    const V t = a > c ? a : c;
                     best = t < best ? t : best;
                 }
+                if (v.span && K >= 1)
+                    for (int a = 0; a + 2 <= b; a++) {              // tiles a .. b - 1 as one RS
+                        const V s0 = hs[((size_t)xp * RR + a) * NP + K - 1];
+                        const V c = bv[(size_t)xp * NPR + (b - 2) * (b - 1) / 2 + a];
+                        const V t = s0 > c ? s0 : c;
+                        best = t < best ? t : best;
+                    }
                 if (best > bt) best = kNo;
-                nxt[e] = best;
-                if (j == r - 1 && best != kNo) hsOk[xp] = 1;
+                hs[((size_t)xp * RR + rowi(b)) * NP + K] = best;
+                if (b == r && best != kNo) hsOk[xp] = 1;
             }
             __syncthreads();
-            V *tmp = cur; cur = nxt; nxt = tmp;
         }
         // column DP: one (i, x') pair per lane, all n at once
         const SmallDiv divX((unsigned)x);
@@ -454,7 +499,7 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
             divX.divmod((unsigned)e, i1, xpu);
             const int i = 1 + (int)i1, xp = (int)xpu;
             if (xp < i - 1 || !hsOk[xp] || !FOk[(i - 1) * (W + 1) + xp]) continue;
-            const V *h = cur + (size_t)xp * NP;
+            const V *h = hs + ((size_t)xp * RR + rowi(r)) * NP;
             const V *f = FT + ((size_t)(i - 1) * (W + 1) + xp) * NP;
             // both rows in registers (NB >= N, entries past N are "none"), loops unrolled
             V fr[NB + 1], hr[NB + 1];
@@ -491,10 +536,12 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
     }
 }
 
-__host__ __device__ inline size_t unit1_lds_bytes(int W, int N, int Cm, int Rm, int Km, int vbytes)
+__host__ __device__ inline size_t unit1_lds_bytes(int W, int N, int Cm, int Rm, int Km, int vbytes, int span)
 {
     const size_t F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
-    return vbytes * (F + 2 * (size_t)W * (N + 1) + (size_t)W * Rm * Km) + 4 * ((size_t)(Cm + 1) * (W + 1) + W);
+    const size_t RR = span ? Rm + 1 : 2, NPR = span ? (size_t)Rm * (Rm - 1) / 2 : 0;
+    return vbytes * (F + RR * W * (N + 1) + (size_t)W * Rm * Km + W * NPR) +
+           4 * ((size_t)(Cm + 1) * (W + 1) + W);
 }
 
 template <int STEP, class V1 = unsigned long long>
@@ -531,7 +578,7 @@ k_lit_units(LitView v, LitWs w)
         if (res1 != kInf) atomicMin(w.hdr, (unsigned long long)res1);
         return;
     }
-    const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, v.Rm, v.Km, STEP, false);
+    const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, v.Rm, v.Km, STEP, false, v.span);
     unit_dp<STEP, false>(v, w, u, L, Yl, r, bt, bq);
     if (threadIdx.x != 0) return;
     long long ct = kInf, cq = kInf;
@@ -587,10 +634,10 @@ k_lit_pick(LitView v, LitWs w)
 
 // ---------------------------------------------------------------------------------------
 // Rebuild the winner and write the result (one wave; lane 0 walks the argmins back).
-__host__ __device__ inline size_t final_lds_bytes(int W, int H, int N, int Cm, int Rm, int Km)
+__host__ __device__ inline size_t final_lds_bytes(int W, int H, int N, int Cm, int Rm, int Km, int span)
 {
     const size_t knap = (size_t)(Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
-    return unit_lds_bytes(W, N, Cm, Rm, Km, 2, true) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile +
+    return unit_lds_bytes(W, N, Cm, Rm, Km, 2, true, span) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile +
            (size_t)Rm * Cm;
 }
 
@@ -607,8 +654,8 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
         unsigned *z = reinterpret_cast<unsigned *>(&res);
         for (size_t e = lane; e < sizeof(trs_result) / 4; e += blockDim.x) z[e] = 0;
     }
-    const UnitLds L = unit_lds(lds_raw, W, N, v.Cm, v.Rm, Km, 2, true);
-    unsigned char *extra = lds_raw + unit_lds_bytes(W, N, v.Cm, v.Rm, Km, 2, true);
+    const UnitLds L = unit_lds(lds_raw, W, N, v.Cm, v.Rm, Km, 2, true, v.span);
+    unsigned char *extra = lds_raw + unit_lds_bytes(W, N, v.Cm, v.Rm, Km, 2, true, v.span);
     const size_t knap = (size_t)(v.Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
     long long *kT = reinterpret_cast<long long *>(extra), *kQ = kT + knap;
     unsigned char *kC = reinterpret_cast<unsigned char *>(kQ + knap);
@@ -694,30 +741,53 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
             res.tile_rows = r;
             for (int i = 0; i <= c; i++) res.col_bd[i] = cx[i];
             for (int j = 0; j <= r; j++) res.row_bd[j] = Yl[j];
-            // slice count of every tile of a strip: DP over its tiles, first minimising k
+            // every tile of a strip: its slice count k, or (blocks) kBlock + b on the top tile of a
+            // block of tiles ending at tile row b and 0 inside it; a DP over the tile-row levels,
+            // tiles first (k ascending) then blocks (a ascending), first minimum kept
+            constexpr int kBlock = 100;                   // above every slice count (k <= H <= 40)
             for (int i = 0; i < c; i++) {
                 const size_t sb = (size_t)wi * v.S + sidx(cx[i], cx[i + 1], W);
                 for (int K = 0; K <= N; K++) { kT[K] = K == 0 ? 0 : kInf; kQ[K] = K == 0 ? 0 : kInf; }
-                for (int j = 0; j < r; j++) {
-                    const size_t tb = (sb * v.R2 + ridx(Yl[j], Yl[j + 1], H)) * Km;
+                for (int b = 1; b <= r; b++) {
+                    const size_t tb = (sb * v.R2 + ridx(Yl[b - 1], Yl[b], H)) * Km;
                     for (int K = 0; K <= N; K++) {
                         long long bt = kInf, bq = kInf;
                         int bk = 0;
                         for (int k = 1; k <= Km && k <= K; k++) {
-                            const long long at = kT[j * (N + 1) + K - k], ct = w.tT[tb + k - 1];
+                            const long long at = kT[(b - 1) * (N + 1) + K - k], ct = w.tT[tb + k - 1];
                             if (at == kInf || ct == kInf) continue;
                             const long long t = at > ct ? at : ct;
-                            const long long q = kQ[j * (N + 1) + K - k] + w.tQ[tb + k - 1];
+                            const long long q = kQ[(b - 1) * (N + 1) + K - k] + w.tQ[tb + k - 1];
                             if (better<2>(q, t, bq, bt)) { bt = t; bq = q; bk = k; }
                         }
-                        kT[(j + 1) * (N + 1) + K] = bt;
-                        kQ[(j + 1) * (N + 1) + K] = bq;
-                        kC[(j + 1) * (N + 1) + K] = (unsigned char)bk;
+                        if (v.span && K >= 1)
+                            for (int a = 0; a + 2 <= b; a++) {
+                                if (!ok(cx[i], cx[i + 1], Yl[a], Yl[b])) continue;
+                                const long long at = kT[a * (N + 1) + K - 1];
+                                if (at == kInf) continue;
+                                const long long bT = rect_at(w.rT, cx[i], cx[i + 1], Yl[a], Yl[b]);
+                                const long long t = at > bT ? at : bT;
+                                const long long q = kQ[a * (N + 1) + K - 1] + rect_at(w.rQ, cx[i], cx[i + 1], Yl[a], Yl[b]);
+                                if (better<2>(q, t, bq, bt)) { bt = t; bq = q; bk = kBlock + a; }
+                            }
+                        kT[b * (N + 1) + K] = bt;
+                        kQ[b * (N + 1) + K] = bq;
+                        kC[b * (N + 1) + K] = (unsigned char)bk;
                     }
                 }
-                for (int j = r, K = ck[i]; j > 0; j--) {
-                    tcnt[(j - 1) * v.Cm + i] = kC[j * (N + 1) + K];
-                    K -= tcnt[(j - 1) * v.Cm + i];
+                for (int j = 0; j < r; j++) tcnt[j * v.Cm + i] = 0;
+                for (int b = r, K = ck[i]; b > 0;) {
+                    const int ch = kC[b * (N + 1) + K];
+                    if (ch < kBlock) {
+                        tcnt[(b - 1) * v.Cm + i] = (unsigned char)ch;
+                        K -= ch;
+                        b -= 1;
+                    } else {
+                        const int a = ch - kBlock;
+                        tcnt[a * v.Cm + i] = (unsigned char)(kBlock + b);
+                        K -= 1;
+                        b = a;
+                    }
                 }
             }
             // tiles in raster order, slices top to bottom: split rows from the tile DP's argmins
@@ -726,6 +796,20 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
             for (int j = 0; j < r; j++)
                 for (int i = 0; i < c; i++) {
                     const int kq = tcnt[j * v.Cm + i];
+                    if (kq == 0) continue;                          // inside a block
+                    if (kq >= kBlock) {                             // a block of tiles j .. b - 1
+                        const int yb = Yl[kq - kBlock];
+                        const long long t = rect_at(w.rT, cx[i], cx[i + 1], Yl[j], yb);
+                        res.rs[nrs][0] = cx[i];
+                        res.rs[nrs][1] = Yl[j];
+                        res.rs[nrs][2] = cx[i + 1];
+                        res.rs[nrs][3] = yb;
+                        res.rs_time[nrs] = t;
+                        if (t > tsel) tsel = t;
+                        qsel += rect_at(w.rQ, cx[i], cx[i + 1], Yl[j], yb);
+                        nrs++;
+                        continue;
+                    }
                     const int y0 = Yl[j], y1 = Yl[j + 1], x0 = cx[i], x1 = cx[i + 1];
                     auto at = [&](int q, int y) { return (size_t)q * (H + 1) + y; };
                     for (int q = 0; q <= kq; q++)
@@ -777,7 +861,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
 // Host side: the plan (geometry, windows, row-boundary list), cached per geometry and
 // parameters with one device copy per device, and the workspace layout.
 struct LitPlan {
-    int W = 0, H = 0, N = 0, Cm = 0, Rm = 0, Km = 0, S = 0, R2 = 0, karea = 0, yrow = 0;
+    int W = 0, H = 0, N = 0, Cm = 0, Rm = 0, Km = 0, S = 0, R2 = 0, karea = 0, yrow = 0, span = 0;
     long long n_win = 0, nY = 0, n_units = 0, n_enumerated = 0;
     std::vector<int> colpx, rowpx;
     std::vector<long long> win;
@@ -807,9 +891,67 @@ trs_status check_args(const trs_frame *f, const trs_search_params *p)
     if (st != TRS_OK) return st;
     if (p->dtile != -1 || p->drs != -1) return TRS_EINVAL;          // the literal space only
     if (p->prune != 0 || (p->min_rs != 0 && p->min_rs != p->n_threads)) return TRS_ENOTIMPL;
+    // (span_tiles is taken: check_space_args has checked it is 0 or 1)
     const int W = (f->width + f->ctu_size - 1) / f->ctu_size, H = (f->height + f->ctu_size - 1) / f->ctu_size;
     if (W > kMaxW || H > kMaxH || p->n_threads > kMaxN) return TRS_ENOTIMPL;
     return TRS_OK;
+}
+
+unsigned long long sat_add(unsigned long long a, unsigned long long b)
+{
+    return a > ~0ull - b ? ~0ull : a + b;
+}
+
+unsigned long long sat_mul(unsigned long long a, unsigned long long b)
+{
+    return a && b > ~0ull / a ? ~0ull : a * b;
+}
+
+unsigned long long binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0;
+    unsigned __int128 c = 1;                                 // exact for n <= 64
+    for (int i = 1; i <= k; i++) c = c * (unsigned)(n - k + i) / (unsigned)i;
+    return c > ~0ull ? ~0ull : (unsigned long long)c;
+}
+
+// |C| of the literal space with blocks of tiles: for every row-boundary vector Y (the plan's
+// list), cover(Y)[n] = ways to cover one tile column with n RS, levels taken one tile row at a
+// time (a tile of h rows into k slices: C(h - 1, k - 1) ways) or as blocks of >= 2 tile rows;
+// then sum over c of C(W - 1, c - 1) times the coefficient of z^N in cover(Y)^c.  Saturating.
+long long span_count(const LitPlan &pl, int max_cols)
+{
+    const int N = pl.N, r_max = pl.Rm;
+    unsigned long long total = 0;
+    std::vector<unsigned long long> cov((size_t)(r_max + 1) * (N + 1)), pw(N + 1), nx(N + 1);
+    for (long long yi = 0; yi < pl.nY; yi++) {
+        const unsigned char *yt = &pl.ytab[(size_t)yi * pl.yrow];
+        const int r = yt[0];
+        std::fill(cov.begin(), cov.end(), 0ull);
+        cov[0] = 1;
+        for (int b = 1; b <= r; b++)
+            for (int n = 0; n <= N; n++) {
+                unsigned long long acc = 0;
+                const int h = yt[1 + b] - yt[b];
+                for (int k = 1; k <= pl.Km && k <= h && k <= n; k++)
+                    acc = sat_add(acc, sat_mul(cov[(size_t)(b - 1) * (N + 1) + n - k], binom(h - 1, k - 1)));
+                if (n >= 1)
+                    for (int a = 0; a + 2 <= b; a++) acc = sat_add(acc, cov[(size_t)a * (N + 1) + n - 1]);
+                cov[(size_t)b * (N + 1) + n] = acc;
+            }
+        std::fill(pw.begin(), pw.end(), 0ull);
+        pw[0] = 1;
+        for (int c = 1; c <= max_cols && c <= pl.W; c++) {
+            std::fill(nx.begin(), nx.end(), 0ull);
+            for (int a = 0; a <= N; a++)
+                if (pw[a])
+                    for (int b = 0; a + b <= N; b++)
+                        nx[a + b] = sat_add(nx[a + b], sat_mul(pw[a], cov[(size_t)r * (N + 1) + b]));
+            pw.swap(nx);
+            total = sat_add(total, sat_mul(binom(pl.W - 1, c - 1), pw[N]));
+        }
+    }
+    return total > (unsigned long long)LLONG_MAX ? LLONG_MAX : (long long)total;
 }
 
 trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
@@ -822,6 +964,7 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
     pl.Rm = std::min(p->max_tile_rows, pl.H);
     pl.Km = std::min(p->max_rs_per_tile, pl.H);
     pl.karea = p->area_k;
+    pl.span = p->span_tiles;
     pl.S = pl.W * (pl.W + 1) / 2;
     pl.R2 = pl.H * (pl.H + 1) / 2;
     pl.colpx.assign(pl.W + 1, 0);
@@ -842,8 +985,8 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
             pl.row_yy[2 * q] = (unsigned char)y0;
             pl.row_yy[2 * q + 1] = (unsigned char)y1;
         }
-    if (unit_lds_bytes(pl.W, pl.N, pl.Cm, pl.Rm, pl.Km, 2, false) > kLdsLimit - 1024 ||
-        final_lds_bytes(pl.W, pl.H, pl.N, pl.Cm, pl.Rm, pl.Km) > kLdsLimit - 4 * 1024 ||
+    if (unit_lds_bytes(pl.W, pl.N, pl.Cm, pl.Rm, pl.Km, 2, false, pl.span) > kLdsLimit - 1024 ||
+        final_lds_bytes(pl.W, pl.H, pl.N, pl.Cm, pl.Rm, pl.Km, pl.span) > kLdsLimit - 4 * 1024 ||
         (size_t)7 * 8 * pl.R2 > kLdsLimit)
         return TRS_ENOTIMPL;
     // windows: distinct RS areas a with N a <= A_total < k N a (all areas when k = 0: one window)
@@ -895,6 +1038,10 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
     pl.nY = (long long)pl.ytab.size() / pl.yrow;
     pl.n_units = pl.n_win * pl.nY;
     if (pl.n_units > kUnitCap) return TRS_ENOSPACE;
+    if (pl.span) {
+        pl.n_enumerated = span_count(pl, p->max_tile_cols);
+        return TRS_OK;
+    }
     trs_search_params lp = *p;
     int32_t dt, dr;
     int64_t n = 0;
@@ -927,7 +1074,7 @@ WsLayout layout(const LitPlan &pl)
 std::vector<long long> key_of(const trs_frame *f, const trs_search_params *p)
 {
     return {f->width, f->height, f->ctu_size, p->n_threads, p->max_tile_cols, p->max_tile_rows,
-            p->max_rs_per_tile, p->area_k};
+            p->max_rs_per_tile, p->area_k, p->span_tiles};
 }
 
 // Plan for (f, p); caller holds g_mu.
@@ -981,7 +1128,7 @@ trs_status view_of(LitPlan &pl, const trs_search_params *p, LitView *v)
     *v = LitView{};
     v->W = pl.W; v->H = pl.H; v->N = pl.N; v->Cm = pl.Cm; v->Rm = pl.Rm; v->Km = pl.Km;
     v->S = pl.S; v->R2 = pl.R2; v->n_win = (int)pl.n_win; v->nY = (int)pl.nY;
-    v->n_units = (int)pl.n_units; v->karea = pl.karea; v->yrow = pl.yrow;
+    v->n_units = (int)pl.n_units; v->karea = pl.karea; v->yrow = pl.yrow; v->span = pl.span;
     v->lam_num = p->lambda_num < 0 ? -1 : p->lambda_num;
     v->lam_den = p->lambda_den;
     v->n_enumerated = pl.n_enumerated;
@@ -1084,20 +1231,20 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
         hipLaunchKernelGGL(k_lit_tiles<1>, gt, dim3(256), tl, stream, v, w);
         mark(2);
         hipLaunchKernelGGL((k_lit_units<1, unsigned>), gu, dim3(64),
-                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 4), stream, v, w);
+                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 4, v.span), stream, v, w);
         hipLaunchKernelGGL((k_lit_units<1, unsigned long long>), gu, dim3(64),
-                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 8), stream, v, w);
+                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 8, v.span), stream, v, w);
         mark(3);
         hipLaunchKernelGGL(k_lit_tiles<2>, gt, dim3(256), tl, stream, v, w);
         mark(4);
-        hipLaunchKernelGGL(k_lit_units<2>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 2, false), stream, v, w);
+        hipLaunchKernelGGL(k_lit_units<2>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 2, false, v.span), stream, v, w);
         mark(5);
         hipLaunchKernelGGL(k_lit_pick, dim3(1), dim3(1024), 0, stream, v, w);
         mark(6);
     } else {
         for (int i = 2; i <= 6; i++) mark(i);
     }
-    hipLaunchKernelGGL(k_lit_final, dim3(1), dim3(64), final_lds_bytes(v.W, v.H, v.N, v.Cm, v.Rm, v.Km),
+    hipLaunchKernelGGL(k_lit_final, dim3(1), dim3(64), final_lds_bytes(v.W, v.H, v.N, v.Cm, v.Rm, v.Km, v.span),
                        stream, v, w, out_dev);
     mark(7);
     if (prof) {

@@ -143,3 +143,20 @@ def test_literal_search_replays_in_a_graph(orc):
         B.trs_literal_search(fr, p, *ins[1], ws, other)       # eager work on the same workspace
         torch.cuda.synchronize()
         assert_same_result(B.read_result(other), ref1, f"eager between replays {rep}")
+
+
+@pytest.mark.parametrize("w,h,N,C,R,K,lam,seed", [(384, 512, 3, 2, 3, 2, (1, 10), 0),
+                                                  (512, 640, 4, 3, 3, 2, (0, 1), 1),
+                                                  (384, 768, 4, 2, 4, 2, (-1, 1), 3),
+                                                  (1920, 1080, 8, 6, 4, 4, (3, 10), 1),
+                                                  (2560, 1440, 8, 6, 4, 4, (1, 10), 2),
+                                                  (1920, 1080, 16, 8, 6, 4, (1, 10), 3)])
+def test_literal_search_with_spanning_blocks_matches_oracle(orc, w, h, N, C, R, K, lam, seed):
+    """RS may also be blocks of complete tiles stacked in one tile column: every field of the
+    GPU result (rectangles in the same order, times, Q, the size of the wider space) equals the
+    oracle's."""
+    luma, f, cost = _inputs(orc, w, h, seed)
+    p = B.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1, span_tiles=1)
+    ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], f["s2"])
+    got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], f["s2"])
+    assert_same_result(got, ref, f"{w}x{h} N {N} spanning")
