@@ -64,6 +64,8 @@ def main():
                          "mlp: training steps of the learned CTU-time predictor; literal: exact search "
                          "of 4K frames over the literal space (every CTU boundary allowed)")
     ap.add_argument("--mlp-batch", type=int, default=65536)
+    ap.add_argument("--span-tiles", type=int, default=0,
+                    help="literal workload: RS may also be blocks of tiles stacked in one tile column")
     ap.add_argument("--prune", type=int, default=0,
                     help="optional pruning rules (bit 0: slice heights, bit 1: mean areas); 0 = the paper's method")
     ap.add_argument("--pipeline", type=int, default=0,
@@ -788,7 +790,7 @@ def run_literal(args):
     F = 8 if args.frames == 64 else args.frames
     frame = B.make_frame(w, h)
     W, H = B.ctu_dims(frame)
-    params = B.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1)
+    params = B.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1, span_tiles=args.span_tiles)
     gen = synth.SequenceGenerator(w, h, 2, 8.0)
     lum_np = [gen.frame(f) for f in range(F + 1)]
     luma = [torch.from_numpy(x.view(np.int16)).cuda() for x in lum_np]
@@ -802,7 +804,6 @@ def run_literal(args):
     ws = torch.empty(B.trs_literal_workspace(frame, params), dtype=torch.uint8, device="cuda")
     out = torch.empty((F + 1, B.RESULT_BYTES), dtype=torch.uint8, device="cuda")
     blend = B.Blend(200, 3, 256)
-    n_space = B.trs_space_size(frame, params)[0]
 
     def step():
         for f in range(1, F + 1):
@@ -855,8 +856,8 @@ def run_literal(args):
         fo = orc.features(lum_np[f])
         c_np, _ = orc.cost_map(fo["tex"], truth[f - 1])
         t1 = time.perf_counter()
-        ref = orc.literal_search(w, h, orc.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1), c_np,
-                                 fo["s1"], fo["s2"])
+        ref = orc.literal_search(w, h, orc.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1,
+                                                       span_tiles=args.span_tiles), c_np, fo["s1"], fo["s2"])
         wall = time.perf_counter() - t1
         keys = ("status", "t_min", "t_sel", "q_sel", "n_enumerated", "tile_cols", "tile_rows",
                 "col_bd", "row_bd", "rs", "rs_time", "t_unif", "q_unif")
@@ -874,7 +875,9 @@ def run_literal(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": f"{F} frames of the 3840x2160 drifting sequence (seed 2), N=8, tiles <= 6x4, "
-                               f"<= 4 RS per tile, lambda 1/10, literal space ({n_space} candidates/frame)",
+                               f"<= 4 RS per tile, lambda 1/10, literal space"
+                               + (" with RS spanning tiles of one tile column" if args.span_tiles else "")
+                               + f" ({res[0]['n_enumerated']} candidates/frame)",
                    "frames_per_step": F},
         "stage_ms_per_frame": {k: round(v, 4) for k, v in st.items()},
         "relaxations_per_frame": {"tiles (each step)": tiles, "units (each step)": units},

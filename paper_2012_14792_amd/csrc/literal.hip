@@ -279,7 +279,7 @@ __device__ inline UnitLds unit_lds(unsigned char *raw, int W, int N, int Cm, int
     return L;
 }
 
-template <int STEP, bool REC>
+template <int STEP, bool REC, bool SPAN>
 __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &L, int *Yl, int &r,
                         long long bt, long long bq)
 {
@@ -302,7 +302,7 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
     }
     auto fi = [&](int i, int x, int n) { return ((size_t)i * (W + 1) + x) * (N + 1) + n; };
     auto keep = [&](long long t, long long q) { return t <= bt && (STEP == 1 || q <= bq); };
-    const int Rm = v.Rm, RR = v.span ? Rm + 1 : 1;
+    const int Rm = v.Rm, RR = SPAN ? Rm + 1 : 1;
     const long long lo = v.win[wi];
     const long long hi = v.karea ? (long long)v.karea * lo : kInf;
     const unsigned long long tau = STEP == 2 ? eq4_bound(w.hdr[0], v.lam_num, v.lam_den) : kNone;
@@ -325,20 +325,19 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
         for (int xp = lane; xp < x; xp += blockDim.x) {
             long long *baseT = L.hsT + (size_t)xp * RR * (N + 1);
             long long *baseQ = STEP == 2 ? L.hsQ + (size_t)xp * RR * (N + 1) : nullptr;
-            auto rowT = [&](int b) { return baseT + (size_t)(v.span ? b : 0) * (N + 1); };
-            auto rowQ = [&](int b) { return baseQ + (size_t)(v.span ? b : 0) * (N + 1); };
+            auto rowT = [&](int b) { return baseT + (size_t)(SPAN ? b : 0) * (N + 1); };
+            auto rowQ = [&](int b) { return baseQ + (size_t)(SPAN ? b : 0) * (N + 1); };
             for (int K = 0; K <= N; K++) {
                 rowT(0)[K] = K == 0 ? 0 : kInf;
                 if (STEP == 2) rowQ(0)[K] = K == 0 ? 0 : kInf;
             }
             const size_t rs0 = (size_t)sidx(xp, x, W) * R2;
             bool any = true;
-            for (int b = 1; b <= r && (any || v.span); b++) {
+            for (int b = 1; b <= r && (any || SPAN); b++) {
                 const long long *tvT = L.tvT + ((size_t)xp * Rm + (b - 1)) * Km;
                 const long long *tvQ = STEP == 2 ? L.tvQ + ((size_t)xp * Rm + (b - 1)) * Km : nullptr;
                 const long long *sT = rowT(b - 1), *sQ = STEP == 2 ? rowQ(b - 1) : nullptr;
                 long long *dT = rowT(b), *dQ = STEP == 2 ? rowQ(b) : nullptr;
-                any = false;
                 for (int K = N; K >= 0; K--) {
                     long long ct = kInf, cq = kInf;
                     for (int k = 1; k <= Km && k <= K; k++) {
@@ -348,25 +347,40 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
                         const long long q = STEP == 2 ? sQ[K - k] + tvQ[k - 1] : 0;
                         if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; }
                     }
-                    if (v.span && K >= 1)
-                        for (int a = 0; a + 2 <= b; a++) {            // tiles a .. b - 1 as one RS
-                            const size_t ri = rs0 + ridx(Yl[a], Yl[b], v.H);
-                            const long long A = w.rA[ri], bT = w.rT[ri];
-                            if (A < lo || A >= hi || (STEP == 2 && (unsigned long long)bT > tau)) continue;
-                            const long long at = rowT(a)[K - 1];
-                            if (at == kInf) continue;
-                            const long long t = at > bT ? at : bT;
-                            const long long q = STEP == 2 ? rowQ(a)[K - 1] + w.rQ[ri] : 0;
-                            if (better<STEP>(q, t, cq, ct)) { ct = t; cq = q; }
-                        }
-                    if (ct != kInf && !REC && !keep(ct, cq)) ct = cq = kInf;
                     dT[K] = ct;
                     if (STEP == 2) dQ[K] = cq;
-                    any |= ct != kInf;
+                }
+                // blocks of tiles a .. b - 1 as one RS, after the single tiles (the same order
+                // per K as taking every choice for one K before the next K)
+                if (SPAN)
+                    for (int a = 0; a + 2 <= b; a++) {
+                        const size_t ri = rs0 + ridx(Yl[a], Yl[b], v.H);
+                        const long long A = w.rA[ri], bT = w.rT[ri];
+                        if (A < lo || A >= hi || (STEP == 2 && (unsigned long long)bT > tau)) continue;
+                        const long long bQ = STEP == 2 ? w.rQ[ri] : 0;
+                        const long long *aT = rowT(a), *aQ = STEP == 2 ? rowQ(a) : nullptr;
+                        for (int K = 1; K <= N; K++) {
+                            const long long at = aT[K - 1];
+                            if (at == kInf) continue;
+                            const long long t = at > bT ? at : bT;
+                            const long long q = STEP == 2 ? aQ[K - 1] + bQ : 0;
+                            if (better<STEP>(q, t, STEP == 2 ? dQ[K] : 0, dT[K])) {
+                                dT[K] = t;
+                                if (STEP == 2) dQ[K] = q;
+                            }
+                        }
+                    }
+                any = false;
+                for (int K = 0; K <= N; K++) {
+                    if (dT[K] != kInf && !REC && !keep(dT[K], STEP == 2 ? dQ[K] : 0)) {
+                        dT[K] = kInf;
+                        if (STEP == 2) dQ[K] = kInf;
+                    }
+                    any |= dT[K] != kInf;
                 }
             }
             if (!any)
-                for (int K = 0; K <= N; K++) rowT(v.span ? r : 0)[K] = kInf;
+                for (int K = 0; K <= N; K++) rowT(SPAN ? r : 0)[K] = kInf;
             L.hsOk[xp] = any;
         }
         __syncthreads();
@@ -378,7 +392,7 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
             int ax = -1, ak = -1;
             for (int xp = i - 1; xp < x; xp++) {
                 if (!L.hsOk[xp] || !L.FOk[(i - 1) * (W + 1) + xp]) continue;
-                const size_t hrow = ((size_t)xp * RR + (v.span ? r : 0)) * (N + 1);
+                const size_t hrow = ((size_t)xp * RR + (SPAN ? r : 0)) * (N + 1);
                 const long long *hT = L.hsT + hrow;
                 for (int K = 1; K <= n; K++) {
                     const size_t fp = fi(i - 1, xp, n - K);
@@ -407,7 +421,7 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
 // value type: 32-bit when the frame's total predicted time is below 2^32 - 1 (every region sum
 // then fits), else 64-bit; its largest value is the "none" sentinel, which max() propagates and
 // min() ignores, so no separate test is needed.
-template <class V, int NB>
+template <class V, int NB, bool SPAN>
 __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char *raw, int *Yl, int &r,
                          long long bt_in, long long *result)
 {
@@ -421,18 +435,19 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
     const int W = v.W, N = v.N, Cm = v.Cm, Km = v.Km, S = v.S, R2 = v.R2, Rm = v.Rm, NP = N + 1;
     const int wi = u / v.nY, yi = u % v.nY;
     const size_t F = (size_t)(Cm + 1) * (W + 1) * NP;
-    // strip rows: all r + 1 tile-row levels when blocks of tiles are allowed (a block ending at
-    // level b starts from level a <= b - 2), else two levels used in turn
-    const int RR = v.span ? Rm + 1 : 2, NPR = v.span ? Rm * (Rm - 1) / 2 : 0;
-    auto rowi = [&](int b) { return v.span ? b : (b & 1); };
+    // strip rows [level][x'][K]: all r + 1 tile-row levels when blocks of tiles are allowed (a
+    // block ending at level b starts from level a <= b - 2), else two levels used in turn
+    const int NPR = SPAN ? Rm * (Rm - 1) / 2 : 0;
+    const int RR = SPAN ? Rm + 1 : 2;
+    auto rowi = [&](int b) { return SPAN ? b : (b & 1); };
     V *FT = reinterpret_cast<V *>(raw);
     V *hs = FT + F;
     V *tv = hs + (size_t)W * RR * NP;
     V *bv = tv + (size_t)W * Rm * Km;                       // block values [x'][pair (a, b)]
     unsigned *FOk = reinterpret_cast<unsigned *>(bv + (size_t)W * NPR);
     unsigned *hsOk = FOk + (size_t)(Cm + 1) * (W + 1);
-    const long long lo = v.win[wi];
-    const long long hi = v.karea ? (long long)v.karea * lo : kInf;
+    const long long lo = SPAN ? v.win[wi] : 0;
+    const long long hi = SPAN && v.karea ? (long long)v.karea * lo : kInf;
     const unsigned char *yt = v.ytab + (size_t)yi * v.yrow;
     r = yt[0];
     for (int j = lane; j <= r; j += blockDim.x) Yl[j] = yt[1 + j];
@@ -450,19 +465,21 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
                 tv[lb + k] = narrow(w.tT[tb + k]);
             }
         }
-        const int npair = v.span ? r * (r - 1) / 2 : 0;
-        for (int e = lane; e < x * npair; e += blockDim.x) {
-            const int xp = e / npair;
-            int pr = e - xp * npair, b = 2;
-            while (pr >= b - 1) { pr -= b - 1; b++; }            // pair index (b-2)(b-1)/2 + a
-            const size_t ri = (size_t)sidx(xp, x, W) * R2 + ridx(Yl[pr], Yl[b], v.H);
-            const long long A = w.rA[ri];
-            bv[(size_t)xp * NPR + (e - xp * npair)] = A >= lo && A < hi ? narrow(w.rT[ri]) : kNo;
+        if constexpr (SPAN) {
+            const int npair = r * (r - 1) / 2;
+            for (int e = lane; e < x * npair; e += blockDim.x) {
+                const int xp = e / npair;
+                int pr = e - xp * npair, b = 2;
+                while (pr >= b - 1) { pr -= b - 1; b++; }        // pair index (b-2)(b-1)/2 + a
+                const size_t ri = (size_t)sidx(xp, x, W) * R2 + ridx(Yl[pr], Yl[b], v.H);
+                const long long A = w.rA[ri];
+                bv[(size_t)xp * NPR + (e - xp * npair)] = A >= lo && A < hi ? narrow(w.rT[ri]) : kNo;
+            }
         }
         for (int e = lane; e < x * NP; e += blockDim.x) {
             unsigned xp, K;
             divNP.divmod((unsigned)e, xp, K);
-            hs[((size_t)xp * RR + rowi(0)) * NP + K] = K == 0 ? V(0) : kNo;
+            hs[((size_t)rowi(0) * W + xp) * NP + K] = K == 0 ? V(0) : kNo;
         }
         for (int xp = lane; xp < x; xp += blockDim.x) hsOk[xp] = 0;
         __syncthreads();
@@ -471,7 +488,7 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
                 unsigned xp, K;
                 divNP.divmod((unsigned)e, xp, K);
                 const V *tj = tv + ((size_t)xp * Rm + (b - 1)) * Km;
-                const V *row = hs + ((size_t)xp * RR + rowi(b - 1)) * NP;
+                const V *row = hs + ((size_t)rowi(b - 1) * W + xp) * NP;
                 V best = kNo;
                 const int kmax = (int)K < Km ? (int)K : Km;
                 for (int k = 1; k <= kmax; k++) {
@@ -479,15 +496,15 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
                     const V t = a > c ? a : c;
                     best = t < best ? t : best;
                 }
-                if (v.span && K >= 1)
-                    for (int a = 0; a + 2 <= b; a++) {              // tiles a .. b - 1 as one RS
-                        const V s0 = hs[((size_t)xp * RR + a) * NP + K - 1];
+                if constexpr (SPAN)
+                    for (int a = 0; a + 2 <= b && K >= 1; a++) {    // tiles a .. b - 1 as one RS
+                        const V s0 = hs[((size_t)a * W + xp) * NP + K - 1];
                         const V c = bv[(size_t)xp * NPR + (b - 2) * (b - 1) / 2 + a];
                         const V t = s0 > c ? s0 : c;
                         best = t < best ? t : best;
                     }
                 if (best > bt) best = kNo;
-                hs[((size_t)xp * RR + rowi(b)) * NP + K] = best;
+                hs[((size_t)rowi(b) * W + xp) * NP + K] = best;
                 if (b == r && best != kNo) hsOk[xp] = 1;
             }
             __syncthreads();
@@ -499,7 +516,7 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
             divX.divmod((unsigned)e, i1, xpu);
             const int i = 1 + (int)i1, xp = (int)xpu;
             if (xp < i - 1 || !hsOk[xp] || !FOk[(i - 1) * (W + 1) + xp]) continue;
-            const V *h = hs + ((size_t)xp * RR + rowi(r)) * NP;
+            const V *h = hs + ((size_t)rowi(r) * W + xp) * NP;
             const V *f = FT + ((size_t)(i - 1) * (W + 1) + xp) * NP;
             // both rows in registers (NB >= N, entries past N are "none"), loops unrolled
             V fr[NB + 1], hr[NB + 1];
@@ -570,16 +587,23 @@ k_lit_units(LitView v, LitWs w)
     if (STEP == 1) {
         __shared__ long long res1;
         if ((w.hdr[4] != 0) != (sizeof(V1) == 4)) return;     // the other launch takes this frame
-        if (v.N <= 8) unit_dp1<V1, 8>(v, w, u, lds_raw, Yl, r, bt, &res1);
-        else if (v.N <= 16) unit_dp1<V1, 16>(v, w, u, lds_raw, Yl, r, bt, &res1);
-        else unit_dp1<V1, kMaxN>(v, w, u, lds_raw, Yl, r, bt, &res1);
+        if (v.span) {
+            if (v.N <= 8) unit_dp1<V1, 8, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
+            else if (v.N <= 16) unit_dp1<V1, 16, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
+            else unit_dp1<V1, kMaxN, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
+        } else {
+            if (v.N <= 8) unit_dp1<V1, 8, false>(v, w, u, lds_raw, Yl, r, bt, &res1);
+            else if (v.N <= 16) unit_dp1<V1, 16, false>(v, w, u, lds_raw, Yl, r, bt, &res1);
+            else unit_dp1<V1, kMaxN, false>(v, w, u, lds_raw, Yl, r, bt, &res1);
+        }
         if (threadIdx.x != 0) return;
         w.uT[u] = res1;                                 // the unit's own minimum (kInf if pruned)
         if (res1 != kInf) atomicMin(w.hdr, (unsigned long long)res1);
         return;
     }
     const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, v.Rm, v.Km, STEP, false, v.span);
-    unit_dp<STEP, false>(v, w, u, L, Yl, r, bt, bq);
+    if (v.span) unit_dp<STEP, false, true>(v, w, u, L, Yl, r, bt, bq);
+    else unit_dp<STEP, false, false>(v, w, u, L, Yl, r, bt, bq);
     if (threadIdx.x != 0) return;
     long long ct = kInf, cq = kInf;
     int bc = 0;
@@ -667,7 +691,10 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
     const unsigned long long tmin = w.hdr[0];
     const bool feasible = tmin != kNone && w.hdr[1] != kNone;
     int r = 0;
-    if (feasible) unit_dp<2, true>(v, w, (int)w.hdr[1], L, Yl, r, kInf, kInf);
+    if (feasible) {
+        if (v.span) unit_dp<2, true, true>(v, w, (int)w.hdr[1], L, Yl, r, kInf, kInf);
+        else unit_dp<2, true, false>(v, w, (int)w.hdr[1], L, Yl, r, kInf, kInf);
+    }
     if (lane == 0) {
         auto rect_at = [&](const long long *a, int x0, int x1, int y0, int y1) {
             return a[(size_t)sidx(x0, x1, W) * v.R2 + ridx(y0, y1, H)];
