@@ -198,8 +198,11 @@ trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
  * boundaries) units, n_enumerated the size of the literal space; status in the result is
  * TRS_ENOFEASIBLE (uniform grid returned) when nothing passes the area rule.  Inputs as in
  * trs_search; workspace: device, at least trs_literal_workspace() bytes, 256-byte aligned.
- * Limits: W <= 64 and H <= 40 CTUs, N <= 32, at most 2^24 units, and LDS tables within 64 KB
- * (TRS_ENOTIMPL / TRS_ENOSPACE beyond); prune must be 0 and min_rs 0 or N (TRS_ENOTIMPL).
+ * With params->span_tiles = 1 an RS may also be a block of two or more complete tiles stacked
+ * in one tile column (n_enumerated then counts that wider space).
+ * Limits: W <= 64 and H <= 40 CTUs, N <= 32, at most 2^24 units, and the per-wave DP tables
+ * within the 160 KB of LDS a gfx950 work-group may use (TRS_ENOTIMPL / TRS_ENOSPACE beyond);
+ * prune must be 0 and min_rs 0 or N (TRS_ENOTIMPL).
  * Returns TRS_OK once enqueued.  Errors: TRS_EINVAL, TRS_ENOTIMPL, TRS_ENOSPACE,
  * TRS_EWORKSPACE, TRS_EDEVICE. */
 trs_status trs_literal_workspace(const trs_frame *frame, const trs_search_params *params,
