@@ -662,7 +662,7 @@ __host__ __device__ inline size_t final_lds_bytes(int W, int H, int N, int Cm, i
 {
     const size_t knap = (size_t)(Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
     return unit_lds_bytes(W, N, Cm, Rm, Km, 2, true, span) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile +
-           (size_t)Rm * Cm;
+           (size_t)Rm * Cm + 16 + 24 * (size_t)(H + 1) * (H + 1) + 16;
 }
 
 __global__ void __launch_bounds__(64)
@@ -817,27 +817,62 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
                     }
                 }
             }
-            // tiles in raster order, slices top to bottom: split rows from the tile DP's argmins
-            int nrs = 0;
-            long long tsel = 0, qsel = 0;
-            for (int j = 0; j < r; j++)
-                for (int i = 0; i < c; i++) {
-                    const int kq = tcnt[j * v.Cm + i];
-                    if (kq == 0) continue;                          // inside a block
-                    if (kq >= kBlock) {                             // a block of tiles j .. b - 1
+        }
+    }
+    __syncthreads();
+    // Tiles in raster order, slices top to bottom.  For a tile cut into slices, all lanes copy
+    // its rectangles' area, time and q into LDS, then lane 0 redoes the tile DP from there and
+    // emits the slices (a block of tiles is emitted at its top tile).
+    if (feasible) {
+        const int c = (int)w.hdr[2];
+        const int wi = (int)(w.hdr[1] / (unsigned long long)v.nY);
+        const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
+        const long long lo = v.win[wi];
+        const long long hi = v.karea ? (long long)v.karea * lo : kInf;
+        constexpr int kBlock = 100;
+        long long *sA = reinterpret_cast<long long *>(                  // after tcnt
+            (reinterpret_cast<uintptr_t>(tcnt + (size_t)v.Rm * v.Cm) + 15) & ~uintptr_t(15));
+        const int HP = H + 1;
+        long long *sT = sA + (size_t)HP * HP, *sQ = sT + (size_t)HP * HP;
+        int nrs = 0;
+        long long tsel = 0, qsel = 0;
+        for (int j = 0; j < r; j++)
+            for (int i = 0; i < c; i++) {
+                const int kq = tcnt[j * v.Cm + i];
+                if (kq == 0) continue;                                  // inside a block
+                const int x0 = cx[i], x1 = cx[i + 1];
+                if (kq >= kBlock) {                                     // a block of tiles j .. b - 1
+                    if (lane == 0) {
                         const int yb = Yl[kq - kBlock];
-                        const long long t = rect_at(w.rT, cx[i], cx[i + 1], Yl[j], yb);
-                        res.rs[nrs][0] = cx[i];
+                        const size_t ri = (size_t)sidx(x0, x1, W) * v.R2 + ridx(Yl[j], yb, H);
+                        const long long t = w.rT[ri];
+                        res.rs[nrs][0] = x0;
                         res.rs[nrs][1] = Yl[j];
-                        res.rs[nrs][2] = cx[i + 1];
+                        res.rs[nrs][2] = x1;
                         res.rs[nrs][3] = yb;
                         res.rs_time[nrs] = t;
                         if (t > tsel) tsel = t;
-                        qsel += rect_at(w.rQ, cx[i], cx[i + 1], Yl[j], yb);
+                        qsel += w.rQ[ri];
                         nrs++;
-                        continue;
                     }
-                    const int y0 = Yl[j], y1 = Yl[j + 1], x0 = cx[i], x1 = cx[i + 1];
+                    continue;
+                }
+                const int y0 = Yl[j], y1 = Yl[j + 1], hh = y1 - y0;
+                const size_t sb = (size_t)sidx(x0, x1, W) * v.R2;
+                for (int e = lane; e < (hh + 1) * (hh + 1); e += blockDim.x) {
+                    const int ya = y0 + e / (hh + 1), yb = y0 + e % (hh + 1);
+                    if (ya >= yb) continue;
+                    const size_t ri = sb + ridx(ya, yb, H);
+                    sA[(ya - y0) * HP + (yb - y0)] = w.rA[ri];
+                    sT[(ya - y0) * HP + (yb - y0)] = w.rT[ri];
+                    sQ[(ya - y0) * HP + (yb - y0)] = w.rQ[ri];
+                }
+                __syncthreads();
+                if (lane == 0) {
+                    auto ok = [&](int ya, int yb) {
+                        const long long A = sA[(ya - y0) * HP + (yb - y0)];
+                        return A >= lo && A < hi && (unsigned long long)sT[(ya - y0) * HP + (yb - y0)] <= tau;
+                    };
                     auto at = [&](int q, int y) { return (size_t)q * (H + 1) + y; };
                     for (int q = 0; q <= kq; q++)
                         for (int y = y0; y <= y1; y++) { fT[at(q, y)] = kInf; fQ[at(q, y)] = kInf; fA[at(q, y)] = -1; }
@@ -846,10 +881,10 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
                     for (int q = 1; q <= kq; q++)
                         for (int y = y0 + q; y <= y1; y++)
                             for (int yp = y0 + q - 1; yp < y; yp++) {
-                                if (fT[at(q - 1, yp)] == kInf || !ok(x0, x1, yp, y)) continue;
-                                const long long st = rect_at(w.rT, x0, x1, yp, y);
+                                if (fT[at(q - 1, yp)] == kInf || !ok(yp, y)) continue;
+                                const long long st = sT[(yp - y0) * HP + (y - y0)];
                                 const long long t = fT[at(q - 1, yp)] > st ? fT[at(q - 1, yp)] : st;
-                                const long long qq = fQ[at(q - 1, yp)] + rect_at(w.rQ, x0, x1, yp, y);
+                                const long long qq = fQ[at(q - 1, yp)] + sQ[(yp - y0) * HP + (y - y0)];
                                 if (better<2>(qq, t, fQ[at(q, y)], fT[at(q, y)])) {
                                     fT[at(q, y)] = t;
                                     fQ[at(q, y)] = qq;
@@ -860,17 +895,20 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
                     rows[kq] = y1;
                     for (int q = kq, y = y1; q > 0; q--) { y = fA[at(q, y)]; rows[q - 1] = y; }
                     for (int q = 0; q < kq; q++) {
-                        const long long t = rect_at(w.rT, x0, x1, rows[q], rows[q + 1]);
+                        const long long t = sT[(rows[q] - y0) * HP + (rows[q + 1] - y0)];
                         res.rs[nrs][0] = x0;
                         res.rs[nrs][1] = rows[q];
                         res.rs[nrs][2] = x1;
                         res.rs[nrs][3] = rows[q + 1];
                         res.rs_time[nrs] = t;
                         if (t > tsel) tsel = t;
-                        qsel += rect_at(w.rQ, x0, x1, rows[q], rows[q + 1]);
+                        qsel += sQ[(rows[q] - y0) * HP + (rows[q + 1] - y0)];
                         nrs++;
                     }
                 }
+                __syncthreads();
+            }
+        if (lane == 0) {
             res.n_rs = nrs;
             res.status = TRS_OK;
             res.t_min = (long long)tmin;
