@@ -561,6 +561,46 @@ __host__ __device__ inline size_t unit1_lds_bytes(int W, int N, int Cm, int Rm, 
            4 * ((size_t)(Cm + 1) * (W + 1) + W);
 }
 
+// True when unit u cannot hold any partition whose RS times are all <= bound (kInf: no time
+// limit), so the unit can be skipped exactly.  Without blocks of tiles the RS of tile row j
+// partition that full-width band, so they number at least ceil(A_j / (k a - 1)) (each RS area is
+// below k a), at most floor(A_j / a) (each is at least a), at most Cm min(Kmax, h_j) (c <= Cm
+// tiles of at most min(Kmax, h_j) slices), and at least ceil(T_j / bound); the bands' ranges
+// must hold N.  One lane per band, sums across the wave.
+__device__ bool unit_infeasible(const LitView &v, const LitWs &w, int u, long long bound)
+{
+    const int lane = threadIdx.x;
+    const int wi = u / v.nY, yi = u % v.nY;
+    const unsigned char *yt = v.ytab + (size_t)yi * v.yrow;
+    const int r = yt[0];
+    const long long a = v.win[wi], k = v.karea;
+    long long lo = 0, hi = 0;
+    for (int j = lane; j < r; j += blockDim.x) {
+        const int y0 = yt[1 + j], y1 = yt[2 + j];
+        const long long A = (long long)v.colpx[v.W] * (v.rowpx[y1] - v.rowpx[y0]);
+        long long mn = 1, mx = (long long)v.Cm * (v.Km < y1 - y0 ? v.Km : y1 - y0);
+        if (k > 0) {
+            const long long amax = k * a - 1;                      // largest area an RS may have
+            const long long need = (A + amax - 1) / amax;
+            mn = need > mn ? need : mn;
+            mx = A / a < mx ? A / a : mx;
+        }
+        if (bound != kInf && bound > 0) {
+            const long long T = w.rT[(size_t)sidx(0, v.W, v.W) * v.R2 + ridx(y0, y1, v.H)];
+            const long long need = (T + bound - 1) / bound;
+            mn = need > mn ? need : mn;
+        }
+        lo += mn;
+        hi += mx < mn ? -(1ll << 40) : mx;                         // an empty range fails the test
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo += __shfl_xor(lo, m, 64);
+        hi += __shfl_xor(hi, m, 64);
+    }
+    return lo > v.N || hi < v.N;
+}
+
 template <int STEP, class V1 = unsigned long long>
 __global__ void __launch_bounds__(64)
 k_lit_units(LitView v, LitWs w)
@@ -572,6 +612,11 @@ k_lit_units(LitView v, LitWs w)
     if (STEP == 1) {
         const unsigned long long best = __atomic_load_n(&w.hdr[0], __ATOMIC_RELAXED);
         if (best != kNone) bt = v.lam_num < 0 ? (long long)best : (long long)eq4_bound(best, v.lam_num, v.lam_den);
+        if ((w.hdr[4] != 0) != (sizeof(V1) == 4)) return;     // the other launch takes this frame
+        if (!v.span && unit_infeasible(v, w, u, bt)) {
+            if (threadIdx.x == 0) w.uT[u] = kInf;
+            return;
+        }
     } else {
         const unsigned long long tmin = w.hdr[0];
         if (tmin == kNone) return;
@@ -586,7 +631,6 @@ k_lit_units(LitView v, LitWs w)
     int r = 0;
     if (STEP == 1) {
         __shared__ long long res1;
-        if ((w.hdr[4] != 0) != (sizeof(V1) == 4)) return;     // the other launch takes this frame
         if (v.span) {
             if (v.N <= 8) unit_dp1<V1, 8, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
             else if (v.N <= 16) unit_dp1<V1, 16, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
