@@ -738,10 +738,12 @@ def run_mlp(args):
     print(json.dumps(out), flush=True)
 
 
-# DP relaxations of the literal-space search and the lane-ops charged to each: a step-1
-# relaxation is a 64-bit max and a 64-bit compare-select (6 lane-ops), a step-2 relaxation adds
-# a 64-bit sum and compares (Q, T~) lexicographically (10 lane-ops).
-LIT_OPS = {1: 6, 2: 10}
+# DP relaxations of the literal-space search and the lane-ops charged to each.  Tile tables: a
+# step-1 relaxation is a 64-bit max and a 64-bit compare-select (6 lane-ops), a step-2 one adds
+# a 64-bit sum and compares (Q, T~) lexicographically (10).  Units: step 1 with 32-bit times is
+# a max and a min (2 lane-ops; 6 with 64-bit times), step 2 on packed (Q, T~) keys is two 64-bit
+# masks, a 64-bit min of them, a 64-bit add and subtract and a 64-bit compare-select (14).
+LIT_OPS = {"tiles1": 6, "tiles2": 10, "units1_u32": 2, "units1_u64": 6, "units2": 14}
 
 
 def literal_relaxations(w, h, N, Cm, Rm, Km, area_k=3, cs=128):
@@ -827,11 +829,13 @@ def run_literal(args):
     step()
     torch.cuda.synchronize()
     B.trs_profile_enable(0)
-    st, runs = B.trs_profile_read_literal()
+    st, runs, (run1, run2) = B.trs_profile_read_literal()
     st = {k: v / runs for k, v in st.items()}
+    run1, run2 = run1 / runs, run2 / runs               # relaxations of the units run, per frame
     tiles, units = literal_relaxations(w, h, N, C, R, K)
-    ops = {"tiles1": tiles * LIT_OPS[1], "units1": units * LIT_OPS[1], "tiles2": tiles * LIT_OPS[2],
-           "units2": units * LIT_OPS[2]}
+    wide = any(int(c.cpu().numpy().view(np.uint32).astype(np.int64).sum()) >= 2**32 - 1 for c in cost[1:])
+    ops = {"tiles1": tiles * LIT_OPS["tiles1"], "tiles2": tiles * LIT_OPS["tiles2"],
+           "units1": run1 * LIT_OPS["units1_u64" if wide else "units1_u32"], "units2": run2 * LIT_OPS["units2"]}
     dom = max(ops, key=lambda k: st[k])
     ach = ops[dom] / (st[dom] * 1e-3) / 1e12
     res = [B.read_result(out[f]) for f in range(1, F + 1)]
@@ -880,7 +884,8 @@ def run_literal(args):
                                + f" ({res[0]['n_enumerated']} candidates/frame)",
                    "frames_per_step": F},
         "stage_ms_per_frame": {k: round(v, 4) for k, v in st.items()},
-        "relaxations_per_frame": {"tiles (each step)": tiles, "units (each step)": units},
+        "relaxations_per_frame": {"tiles (each step)": tiles, "units (each step, every unit)": units,
+                                  "units run (step 1)": round(run1), "units run (step 2)": round(run2)},
         "roofline": {"bound": "alu", "kernel": {"units1": "k_lit_units<1>", "units2": "k_lit_units<2>",
                                                 "tiles1": "k_lit_tiles<1>", "tiles2": "k_lit_tiles<2>"}[dom],
                      "achieved": round(ach, 3), "peak": PEAK_ALU_TOPS, "unit": "T lane-ops/s",

@@ -195,12 +195,13 @@ trs_status trs_search(const trs_frame *frame, const trs_search_params *params,
  * tiles and column boundaries.  Among partitions with equal (Q, T~(P)) it returns the first in
  * the order (window, r, row boundaries, c) of that decomposition, not the smallest canonical
  * rank: rank, n_feasible and uniform_rank are -1, n_step2 is the number of (window, row
- * boundaries) units, n_enumerated the size of the literal space; status in the result is
+ * boundaries) units searched (those whose tile-row bands can hold N RS by area and slice
+ * count), n_enumerated the size of the literal space; status in the result is
  * TRS_ENOFEASIBLE (uniform grid returned) when nothing passes the area rule.  Inputs as in
  * trs_search; workspace: device, at least trs_literal_workspace() bytes, 256-byte aligned.
  * With params->span_tiles = 1 an RS may also be a block of two or more complete tiles stacked
  * in one tile column (n_enumerated then counts that wider space).
- * Limits: W <= 64 and H <= 40 CTUs, N <= 32, at most 2^24 units, and the per-wave DP tables
+ * Limits: W <= 64 and H <= 40 CTUs, N <= 32, at most 2^24 units, and the per-unit DP tables
  * within the 160 KB of LDS a gfx950 work-group may use (TRS_ENOTIMPL / TRS_ENOSPACE beyond);
  * prune must be 0 and min_rs 0 or N (TRS_ENOTIMPL).
  * Returns TRS_OK once enqueued.  Errors: TRS_EINVAL, TRS_ENOTIMPL, TRS_ENOSPACE,
@@ -215,9 +216,12 @@ trs_status trs_literal_search(const trs_frame *frame, const trs_search_params *p
 /* Per-stage durations (ms, summed) of the trs_literal_search calls made while profiling was
  * on (trs_profile_enable), then forgets them: ms[0] prefix sums and rectangle values, ms[1]
  * step-1 tile tables, ms[2] step-1 units, ms[3] step-2 tile tables, ms[4] step-2 units,
- * ms[5] unit reduction, ms[6] rebuild and result; *runs = number of searches.  Waits for the
- * last recorded event.  Errors: TRS_EINVAL, TRS_EDEVICE. */
-trs_status trs_profile_read_literal(double *ms, int64_t *runs);
+ * ms[5] unit reduction, ms[6] rebuild and result; *runs = number of searches; relax[0] and
+ * relax[1] = DP relaxations (pair combinations, counted from the loop bounds) of the units that
+ * step 1 and step 2 ran, the units skipped by a bound left out.  Each profiled search holds 16
+ * bytes of device memory until this call.  Waits for the last recorded event.
+ * Errors: TRS_EINVAL, TRS_EDEVICE. */
+trs_status trs_profile_read_literal(double *ms, int64_t *runs, int64_t *relax);
 
 /* The whole per-frame path in one call (Fig. 3 of the paper: current-frame luma and the
  * co-located previous times in, partition out): trs_features, trs_cost_map and trs_search

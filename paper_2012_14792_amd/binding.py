@@ -114,7 +114,8 @@ def lib():
         L.trs_literal_workspace.restype = S
         L.trs_literal_search.argtypes = L.trs_search.argtypes
         L.trs_literal_search.restype = S
-        L.trs_profile_read_literal.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.trs_profile_read_literal.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64)]
         L.trs_profile_read_literal.restype = S
         L.trs_partition.argtypes = [ctypes.POINTER(Frame), ctypes.POINTER(SearchParams), P,
                                     ctypes.c_int64, P, Blend, Feat, P, P, P, ctypes.c_size_t, P, P]
@@ -367,12 +368,14 @@ def trs_literal_search(frame: Frame, params: SearchParams, cost, s1, s2, workspa
 LITERAL_STAGES = ("prefix_rects", "tiles1", "units1", "tiles2", "units2", "pick", "final")
 
 
-def trs_profile_read_literal() -> tuple[dict, int]:
-    """Summed per-stage ms of the literal searches made while profiling was on, and their count."""
+def trs_profile_read_literal() -> tuple[dict, int, tuple[int, int]]:
+    """Summed per-stage ms of the literal searches made while profiling was on, their count, and
+    the DP relaxations of the units that step 1 and step 2 ran (summed over the searches)."""
     ms = (ctypes.c_double * len(LITERAL_STAGES))()
     n = ctypes.c_int64()
-    check(lib().trs_profile_read_literal(ms, ctypes.byref(n)), "trs_profile_read_literal")
-    return dict(zip(LITERAL_STAGES, list(ms))), n.value
+    relax = (ctypes.c_int64 * 2)()
+    check(lib().trs_profile_read_literal(ms, ctypes.byref(n), relax), "trs_profile_read_literal")
+    return dict(zip(LITERAL_STAGES, list(ms))), n.value, (relax[0], relax[1])
 
 
 def _feat(feats: dict) -> Feat:

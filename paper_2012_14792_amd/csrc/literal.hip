@@ -18,7 +18,7 @@
 //                 edge x of the strips, all state in LDS;
 //   k_lit_pick    the best unit: step 1 by an atomic minimum of T~min, step 2 by a reduction
 //                 over (Q, T~(P), unit);
-//   k_lit_final   one wave redoes the winning unit keeping the argmins, rebuilds boundaries
+//   k_lit_final   one work-group redoes the winning unit keeping the argmins, rebuilds boundaries
 //                 and splits, and writes the trs_result.
 // Ties follow the order (window, r, Y lexicographic, c) and the first minimising choice in
 // ascending loop order inside each DP.  The canonical rank is not computed (-1), nor the count
@@ -50,25 +50,31 @@ constexpr long long kUnitCap = 1ll << 24;
 
 // Device view of the host tables (by value).
 struct LitView {
-    int W, H, N, Cm, Rm, Km, S, R2, n_win, nY, n_units, karea, lam_num, lam_den, yrow, span;
+    int W, H, N, Cm, Rm, Km, S, R2, n_win, nY, n_units, n_wlive, karea, lam_num, lam_den, yrow, span;
     long long n_enumerated;
     const int *colpx, *rowpx;           // pixel prefix sums
     const long long *win;               // window lower bounds a (upper bound k a, or none)
     const unsigned char *ytab;          // per Y: r, then Y_0 .. Y_r (yrow bytes per entry)
     const unsigned char *strip_xy;      // per strip: x0, x1
     const unsigned char *row_yy;        // per row pair: y0, y1
-    const int *worder;                  // windows in dispatch order (likeliest to win first)
+    const int *ulist;                   // units kept (index window * nY + Y), ascending
+    const int *dorder;                  // positions in ulist in dispatch order
+    const int *wlive;                   // windows holding a kept unit, ascending
+    unsigned long long *work;           // while profiling: relaxations of the units run, per step
+    long long relaxA, relaxB;           // a unit of r tile rows has r relaxA + relaxB of them
 };
 
 struct LitWs {
     unsigned long long *hdr;            // [0] T~min, [1] winning unit, [2] its column count,
                                         // [3] least Q of a unit so far (step-2 pruning bound),
-                                        // [4] 1 when the frame's total time is below 2^32 - 1
+                                        // [4] 1 when the frame's total time is below 2^32 - 1,
+                                        // [5] 1 when some rectangle has q < 0
     long long *sat;                     // 3 inclusive prefix sums, (H + 1) x (W + 1) each
     long long *rA, *rT, *rQ;            // per rectangle [S][R2]: area, time, q
     long long *tT, *tQ;                 // per [window][strip][row pair][k - 1]
     long long *uQ, *uT;                 // per unit: best (Q, T~) of step 2
     int *uC;                            // per unit: its column count
+    long long *wT;                      // per window: least step-1 result of its units
 };
 
 __host__ __device__ __forceinline__ int sidx(int x0, int x1, int W)
@@ -121,7 +127,10 @@ k_lit_sat(LitView v, LitWs w, const uint32_t *__restrict__ cost, const uint32_t 
         w.hdr[2] = 0;
         w.hdr[3] = kNone;
         w.hdr[4] = 0;
+        w.hdr[5] = 0;
+        if (v.work) { v.work[0] = 0; v.work[1] = 0; }
     }
+    for (int i = threadIdx.x; i < v.n_win; i += blockDim.x) w.wT[i] = kInf;
     // rows: running sums along x
     for (int t = threadIdx.x; t < 3 * (H + 1); t += blockDim.x) {
         const int a = t / (H + 1), y = t % (H + 1);
@@ -167,7 +176,9 @@ k_lit_rects(LitView v, LitWs w)
     const long long a1 = rect(w.sat + P), a2 = rect(w.sat + 2 * (size_t)P);
     w.rA[i] = A;
     w.rT[i] = rect(w.sat);
-    w.rQ[i] = a2 - (long long)floor_sq_div((unsigned long long)a1, (unsigned)A);
+    const long long q = a2 - (long long)floor_sq_div((unsigned long long)a1, (unsigned)A);
+    w.rQ[i] = q;
+    if (q < 0) w.hdr[5] = 1;            // statistics no real pixels have (S1^2 > n S2)
 }
 
 // ---------------------------------------------------------------------------------------
@@ -179,7 +190,7 @@ k_lit_tiles(LitView v, LitWs w)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int R2 = v.R2, H = v.H, Km = v.Km;
-    const int wi = blockIdx.x / v.S, s = blockIdx.x % v.S;
+    const int wi = v.wlive[blockIdx.x / v.S], s = blockIdx.x % v.S;
     long long *sA = reinterpret_cast<long long *>(lds_raw);
     long long *sT = sA + R2;
     long long *sQ = sT + R2;
@@ -190,6 +201,9 @@ k_lit_tiles(LitView v, LitWs w)
         const unsigned long long tmin = w.hdr[0];
         if (tmin == kNone) return;
         tau = eq4_bound(tmin, v.lam_num, v.lam_den);
+        // no unit of this window reaches step 2 (each unit's step-1 result is exact whenever it
+        // is within the bound step 1 pruned with, which is at least tau)
+        if (v.lam_num >= 0 && (unsigned long long)w.wT[wi] > tau) return;
     }
     const long long lo = v.win[wi];
     const long long hi = v.karea ? (long long)v.karea * lo : kInf;
@@ -231,15 +245,16 @@ k_lit_tiles(LitView v, LitWs w)
 }
 
 // ---------------------------------------------------------------------------------------
-// The column DP of one unit (window, Y) by one wave.  LDS: strip values hs[x'][K] for the
+// The column DP of one unit (window, Y), serial per state: step 2 and the rebuild when (Q, T~)
+// does not fit one 64-bit key.  LDS: strip values hs[x'][K] for the
 // strips ending at the current x, the DP table F[i][x][n], a flag per hs row and per (i, x) row
 // telling whether it holds a finite value, and with REC the argmins.
 //
 // Pruning (exact): a state whose T~ exceeds bt, or whose Q exceeds bq, becomes infinite.  Step
 // 1 passes the Eq. 4 bound of the best T~min found so far (or that T~min when lambda is
 // infinite), so every unit whose own minimum is within the final bound still reports it exactly;
-// step 2 passes the best Q found so far (Q of a partial partition only grows, as every RS has
-// q >= 0).  A partition through a pruned state cannot be the optimum.  REC (the rebuild) prunes
+// step 2 passes the best Q found so far when every rectangle has q >= 0 (Q of a partial
+// partition then only grows), else none.  A partition through a pruned state cannot be the optimum.  REC (the rebuild) prunes
 // nothing, so its argmins are those of the full DP.
 struct UnitLds {
     long long *hsT, *hsQ, *FT, *FQ;
@@ -414,23 +429,73 @@ __device__ void unit_dp(const LitView &v, const LitWs &w, int u, const UnitLds &
     }
 }
 
-// Step 1 without argmins, balanced over the lanes: the strip DP takes one (x', K) pair per lane
-// (rows of hs double-buffered per tile), the column DP one (i, x') pair per lane, each folding
-// its candidates for every n into F[i][x][n] with an LDS atomic minimum.  Same values as
-// unit_dp<1, false>: the minimum of a set does not depend on the order it is taken in.  V is the
-// value type: 32-bit when the frame's total predicted time is below 2^32 - 1 (every region sum
-// then fits), else 64-bit; its largest value is the "none" sentinel, which max() propagates and
-// min() ignores, so no separate test is needed.
-template <class V, int NB, bool SPAN>
-__device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char *raw, int *Yl, int &r,
-                         long long bt_in, long long *result)
+// Step-2 values as one 64-bit key Q 2^tb + T~ (T~ < 2^tb): keys order as the pairs (Q, T~) do
+// lexicographically, and joining two disjoint parts (Q adds, T~ takes the larger) is
+// a + b - min(a mod 2^tb, b mod 2^tb).  It applies when every key stays below 2^61: the Q of a
+// partial partition is at most the frame's S2 (q = S2 - floor(S1^2 / n) of an RS lies in
+// [0, S2] by Cauchy-Schwarz when the statistics are those of real pixels, which k_lit_rects
+// checks), and every T~ is at most the Eq. 4 bound and the frame's total.  kBig = 2^62 is
+// "none"; a join involving it lands at or above kBig without wrapping (at most 2^63), and every
+// stored value is either a key or exactly kBig.
+constexpr unsigned long long kBig = 1ull << 62;
+
+struct Pack {
+    unsigned tb;
+    unsigned long long mask;
+    __device__ unsigned long long key(long long q, long long t) const
+    {
+        return t == kInf ? kBig : ((unsigned long long)q << tb) | (unsigned long long)t;
+    }
+};
+
+__device__ bool pack_for(const LitView &v, const LitWs &w, Pack &p)
 {
-    constexpr V kNo = ~V(0);
-    // a value maps to the sentinel when it is infinite or does not fit below it
+    if (w.hdr[5] != 0) return false;                     // some rectangle has q < 0
+    const size_t P = (size_t)(v.W + 1) * (v.H + 1);
+    const unsigned long long Ttot = (unsigned long long)w.sat[P - 1];
+    const unsigned long long S2 = (unsigned long long)w.sat[3 * P - 1];
+    unsigned long long cap = eq4_bound(w.hdr[0], v.lam_num, v.lam_den);
+    cap = cap < Ttot ? cap : Ttot;
+    int tb = 64 - __clzll(cap);                          // cap < 2^tb
+    tb = tb < 1 ? 1 : tb;
+    if (tb > 60 || S2 >= (1ull << (61 - tb))) return false;
+    p.tb = (unsigned)tb;
+    p.mask = (1ull << tb) - 1;
+    return true;
+}
+
+// Step 1 (V: 32- or 64-bit T~) and step 2 (V: 64-bit keys) balanced over the lanes: the strip
+// DP takes one (x', K) pair per lane (rows of hs double-buffered per tile), the column DP one
+// (i, x') pair per lane, each folding its candidates for every n into F[i][x][n] with an LDS
+// atomic minimum.  Same values as unit_dp: the minimum of a set does not depend on the order it
+// is taken in.  In step 1 the largest value of V is "none" (a frame whose total time is below
+// 2^32 - 1 runs with 32-bit values: every region sum fits), which max() propagates and min()
+// ignores.  REC (step 2 only) keeps argmins equal to the serial DP's first minimum in ascending
+// (x', K) order: once F[.][x][.] is final, each (i, x') pair finds its first K that reaches the
+// value, and an atomic minimum of x' 64 + K picks the first pair.
+template <class V, int NB, bool SPAN, int STEP, bool REC>
+__device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char *raw, int *Yl, int &r,
+                         long long bound, const Pack &pk, unsigned char *AX, unsigned char *AK,
+                         unsigned *AXK, long long *result, int *result_c)
+{
+    constexpr V kNo = STEP == 1 ? ~V(0) : V(kBig);
+    // step 1: a value maps to the sentinel when it is infinite or does not fit below it
     auto narrow = [&](long long t) {
         return (t == kInf || (unsigned long long)t >= (unsigned long long)kNo) ? kNo : (V)t;
     };
-    const V bt = bt_in == kInf ? V(kNo - 1) : (narrow(bt_in) == kNo ? V(kNo - 1) : (V)bt_in);
+    auto join = [&](V a, V b) -> V {
+        if constexpr (STEP == 1) return a > b ? a : b;
+        else {
+            const V ta = a & pk.mask, tb = b & pk.mask;
+            return a + b - (ta < tb ? ta : tb);
+        }
+    };
+    V bt;                                                // values above it are pruned
+    if constexpr (STEP == 1)
+        bt = bound == kInf ? V(kNo - 1) : (narrow(bound) == kNo ? V(kNo - 1) : (V)bound);
+    else
+        bt = bound == kInf || (unsigned long long)bound >= (kBig >> pk.tb) ? V(kNo - 1)
+                                                                          : (((V)bound << pk.tb) | pk.mask);
     const int lane = threadIdx.x;
     const int W = v.W, N = v.N, Cm = v.Cm, Km = v.Km, S = v.S, R2 = v.R2, Rm = v.Rm, NP = N + 1;
     const int wi = u / v.nY, yi = u % v.nY;
@@ -448,11 +513,14 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
     unsigned *hsOk = FOk + (size_t)(Cm + 1) * (W + 1);
     const long long lo = SPAN ? v.win[wi] : 0;
     const long long hi = SPAN && v.karea ? (long long)v.karea * lo : kInf;
+    const unsigned long long tau = STEP == 2 ? eq4_bound(w.hdr[0], v.lam_num, v.lam_den) : kNone;
     const unsigned char *yt = v.ytab + (size_t)yi * v.yrow;
     r = yt[0];
     for (int j = lane; j <= r; j += blockDim.x) Yl[j] = yt[1 + j];
     for (size_t e = lane; e < F; e += blockDim.x) FT[e] = e == 0 ? V(0) : kNo;
     for (int e = lane; e < (Cm + 1) * (W + 1); e += blockDim.x) FOk[e] = e == 0;
+    if constexpr (REC)
+        for (int e = lane; e < (Cm + 1) * NP; e += blockDim.x) AXK[e] = ~0u;
     __syncthreads();
     const SmallDiv divR((unsigned)r), divNP((unsigned)NP);
     for (int x = 1; x <= W; x++) {
@@ -462,7 +530,8 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
             const size_t tb = (((size_t)wi * S + sidx(xp, x, W)) * R2 + ridx(Yl[j], Yl[j + 1], v.H)) * Km;
             const size_t lb = ((size_t)xp * Rm + j) * Km;
             for (int k = 0; k < Km; k++) {
-                tv[lb + k] = narrow(w.tT[tb + k]);
+                if constexpr (STEP == 1) tv[lb + k] = narrow(w.tT[tb + k]);
+                else tv[lb + k] = pk.key(w.tQ[tb + k], w.tT[tb + k]);
             }
         }
         if constexpr (SPAN) {
@@ -473,7 +542,12 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
                 while (pr >= b - 1) { pr -= b - 1; b++; }        // pair index (b-2)(b-1)/2 + a
                 const size_t ri = (size_t)sidx(xp, x, W) * R2 + ridx(Yl[pr], Yl[b], v.H);
                 const long long A = w.rA[ri];
-                bv[(size_t)xp * NPR + (e - xp * npair)] = A >= lo && A < hi ? narrow(w.rT[ri]) : kNo;
+                V val = kNo;
+                if (A >= lo && A < hi) {
+                    if constexpr (STEP == 1) val = narrow(w.rT[ri]);
+                    else if ((unsigned long long)w.rT[ri] <= tau) val = pk.key(w.rQ[ri], w.rT[ri]);
+                }
+                bv[(size_t)xp * NPR + (e - xp * npair)] = val;
             }
         }
         for (int e = lane; e < x * NP; e += blockDim.x) {
@@ -492,15 +566,14 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
                 V best = kNo;
                 const int kmax = (int)K < Km ? (int)K : Km;
                 for (int k = 1; k <= kmax; k++) {
-                    const V a = row[K - k], c = tj[k - 1];
-                    const V t = a > c ? a : c;
+                    const V t = join(row[K - k], tj[k - 1]);
                     best = t < best ? t : best;
                 }
                 if constexpr (SPAN)
                     for (int a = 0; a + 2 <= b && K >= 1; a++) {    // tiles a .. b - 1 as one RS
                         const V s0 = hs[((size_t)a * W + xp) * NP + K - 1];
                         const V c = bv[(size_t)xp * NPR + (b - 2) * (b - 1) / 2 + a];
-                        const V t = s0 > c ? s0 : c;
+                        const V t = join(s0, c);
                         best = t < best ? t : best;
                     }
                 if (best > bt) best = kNo;
@@ -509,7 +582,9 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
             }
             __syncthreads();
         }
-        // column DP: one (i, x') pair per lane, all n at once
+        // column DP: one (i, x') pair per lane, all n at once (x' varies fastest across lanes:
+        // measured faster than i fastest, whose scattered row reads cost more than the atomic
+        // conflicts it removes)
         const SmallDiv divX((unsigned)x);
         for (int e = lane; e < Cm * x; e += blockDim.x) {
             unsigned i1, xpu;
@@ -531,7 +606,7 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
                 V best = kNo;
 #pragma unroll
                 for (int K = 1; K <= n; K++) {
-                    const V t = fr[n - K] > hr[K] ? fr[n - K] : hr[K];
+                    const V t = join(fr[n - K], hr[K]);
                     best = t < best ? t : best;
                 }
                 if (n <= N && best <= bt) {
@@ -542,14 +617,51 @@ __device__ void unit_dp1(const LitView &v, const LitWs &w, int u, unsigned char 
             if (any) FOk[i * (W + 1) + x] = 1;
         }
         __syncthreads();
+        if constexpr (REC) {
+            for (int e = lane; e < Cm * x; e += blockDim.x) {
+                unsigned i1, xpu;
+                divX.divmod((unsigned)e, i1, xpu);
+                const int i = 1 + (int)i1, xp = (int)xpu;
+                if (xp < i - 1 || !hsOk[xp] || !FOk[(i - 1) * (W + 1) + xp]) continue;
+                const V *h = hs + ((size_t)rowi(r) * W + xp) * NP;
+                const V *f = FT + ((size_t)(i - 1) * (W + 1) + xp) * NP;
+                const V *g = FT + ((size_t)i * (W + 1) + x) * NP;
+                for (int n = 1; n <= N; n++) {
+                    const V target = g[n];
+                    if (target == kNo) continue;
+                    for (int K = 1; K <= n; K++)
+                        if (join(f[n - K], h[K]) == target) {
+                            atomicMin(AXK + i * NP + n, (unsigned)(xp * 64 + K));
+                            break;
+                        }
+                }
+            }
+            __syncthreads();
+            for (int e = lane; e < Cm * NP; e += blockDim.x) {
+                const int i = 1 + e / NP, n = e % NP;
+                const unsigned c = AXK[i * NP + n];
+                const size_t fo = ((size_t)i * (W + 1) + x) * NP + n;
+                AX[fo] = c == ~0u ? 0xff : (unsigned char)(c / 64);
+                AK[fo] = c == ~0u ? 0xff : (unsigned char)(c % 64);
+                AXK[i * NP + n] = ~0u;
+            }
+            __syncthreads();
+        }
     }
     if (lane == 0) {
         V best = kNo;
+        int bc = 0;
         for (int c = 1; c <= Cm; c++) {
             const V t = FT[((size_t)c * (W + 1) + W) * NP + N];
-            best = t < best ? t : best;
+            if (t < best) { best = t; bc = c; }
         }
-        *result = best == kNo ? kInf : (long long)best;
+        if constexpr (STEP == 1) {
+            result[0] = best == kNo ? kInf : (long long)best;
+        } else {
+            result[0] = best == kNo ? kInf : (long long)(best >> pk.tb);
+            result[1] = best == kNo ? kInf : (long long)(best & pk.mask);
+        }
+        *result_c = best == kNo ? 0 : bc;
     }
 }
 
@@ -561,21 +673,40 @@ __host__ __device__ inline size_t unit1_lds_bytes(int W, int N, int Cm, int Rm, 
            4 * ((size_t)(Cm + 1) * (W + 1) + W);
 }
 
+// LDS of step 2: the serial DP's layout, or the packed one when the keys fit (decided at run
+// time, so both must fit).
+__host__ __device__ inline size_t unit2_lds_bytes(int W, int N, int Cm, int Rm, int Km, int span)
+{
+    const size_t a = unit_lds_bytes(W, N, Cm, Rm, Km, 2, false, span), b = unit1_lds_bytes(W, N, Cm, Rm, Km, 8, span);
+    return a > b ? a : b;
+}
+
+// LDS of the rebuild's DP: the serial DP with argmins, or the packed DP followed by its argmin
+// bytes and the per-x atomic scratch.
+__host__ __device__ inline size_t rec_lds_bytes(int W, int N, int Cm, int Rm, int Km, int span)
+{
+    const size_t F = (size_t)(Cm + 1) * (W + 1) * (N + 1);
+    const size_t a = unit_lds_bytes(W, N, Cm, Rm, Km, 2, true, span);
+    const size_t b = ((unit1_lds_bytes(W, N, Cm, Rm, Km, 8, span) + 15) & ~size_t(15)) + ((2 * F + 15) & ~size_t(15)) +
+                     4 * (size_t)(Cm + 1) * (N + 1);
+    return ((a > b ? a : b) + 15) & ~size_t(15);
+}
+
 // True when unit u cannot hold any partition whose RS times are all <= bound (kInf: no time
 // limit), so the unit can be skipped exactly.  Without blocks of tiles the RS of tile row j
 // partition that full-width band, so they number at least ceil(A_j / (k a - 1)) (each RS area is
 // below k a), at most floor(A_j / a) (each is at least a), at most Cm min(Kmax, h_j) (c <= Cm
 // tiles of at most min(Kmax, h_j) slices), and at least ceil(T_j / bound); the bands' ranges
-// must hold N.  One lane per band, sums across the wave.
+// must hold N.  One lane per band, sums across the wave; every wave computes the same answer.
 __device__ bool unit_infeasible(const LitView &v, const LitWs &w, int u, long long bound)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int wi = u / v.nY, yi = u % v.nY;
     const unsigned char *yt = v.ytab + (size_t)yi * v.yrow;
     const int r = yt[0];
     const long long a = v.win[wi], k = v.karea;
     long long lo = 0, hi = 0;
-    for (int j = lane; j < r; j += blockDim.x) {
+    for (int j = lane; j < r; j += 64) {
         const int y0 = yt[1 + j], y1 = yt[2 + j];
         const long long A = (long long)v.colpx[v.W] * (v.rowpx[y1] - v.rowpx[y0]);
         long long mn = 1, mx = (long long)v.Cm * (v.Km < y1 - y0 ? v.Km : y1 - y0);
@@ -601,68 +732,94 @@ __device__ bool unit_infeasible(const LitView &v, const LitWs &w, int u, long lo
     return lo > v.N || hi < v.N;
 }
 
-template <int STEP, class V1 = unsigned long long>
-__global__ void __launch_bounds__(64)
+// One work-group of BS threads per unit: one wave in step 1 (many units run, throughput counts),
+// four in step 2 (few units run, their latency counts).  NB: the register rows' length bucket
+// (N <= NB), a template parameter of the kernel so that each launch is allocated the registers
+// of its own bucket only.  The pruning bounds are read once and shared through LDS: the waves
+// of a work-group must take the same branches around their barriers.
+template <int STEP, class V1, int NB, int BS = STEP == 1 ? 64 : 256>
+__global__ void __launch_bounds__(BS)
 k_lit_units(LitView v, LitWs w)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int Yl[kMaxH + 1];
-    const int u = v.worder[blockIdx.x / v.nY] * v.nY + (int)(blockIdx.x % v.nY);
+    __shared__ unsigned long long bound_sh;
+    const int p = v.dorder[blockIdx.x];                 // position in the kept list
+    const int u = v.ulist[p];                           // unit: window u / nY, row boundaries u % nY
+    if (threadIdx.x == 0)
+        bound_sh = __atomic_load_n(&w.hdr[STEP == 1 ? 0 : 3], __ATOMIC_RELAXED);
+    __syncthreads();
     long long bt = kInf, bq = kInf;
     if (STEP == 1) {
-        const unsigned long long best = __atomic_load_n(&w.hdr[0], __ATOMIC_RELAXED);
+        const unsigned long long best = bound_sh;
         if (best != kNone) bt = v.lam_num < 0 ? (long long)best : (long long)eq4_bound(best, v.lam_num, v.lam_den);
         if ((w.hdr[4] != 0) != (sizeof(V1) == 4)) return;     // the other launch takes this frame
         if (!v.span && unit_infeasible(v, w, u, bt)) {
-            if (threadIdx.x == 0) w.uT[u] = kInf;
+            if (threadIdx.x == 0) w.uT[p] = kInf;
             return;
         }
     } else {
         const unsigned long long tmin = w.hdr[0];
         if (tmin == kNone) return;
         const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
-        if (v.lam_num >= 0 && (unsigned long long)w.uT[u] > tau) {       // no candidate within Eq. 4
-            if (threadIdx.x == 0) { w.uQ[u] = kInf; w.uT[u] = kInf; w.uC[u] = 0; }
+        if (v.lam_num >= 0 && (unsigned long long)w.uT[p] > tau) {       // no candidate within Eq. 4
+            if (threadIdx.x == 0) { w.uQ[p] = kInf; w.uT[p] = kInf; w.uC[p] = 0; }
             return;
         }
-        const unsigned long long qb = __atomic_load_n(&w.hdr[3], __ATOMIC_RELAXED);
-        if (qb != kNone) bq = (long long)qb;
+        // the Q bound prunes exactly only while every q >= 0 (Q of a partial partition then
+        // only grows)
+        const unsigned long long qb = bound_sh;
+        if (qb != kNone && w.hdr[5] == 0) bq = (long long)qb;
     }
+    if (v.work && threadIdx.x == 0)
+        atomicAdd(v.work + (STEP - 1), (unsigned long long)(v.ytab[(size_t)(u % v.nY) * v.yrow] * v.relaxA + v.relaxB));
     int r = 0;
+    __shared__ long long res[2];
+    __shared__ int res_c;
+    const Pack none{};
     if (STEP == 1) {
-        __shared__ long long res1;
-        if (v.span) {
-            if (v.N <= 8) unit_dp1<V1, 8, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
-            else if (v.N <= 16) unit_dp1<V1, 16, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
-            else unit_dp1<V1, kMaxN, true>(v, w, u, lds_raw, Yl, r, bt, &res1);
-        } else {
-            if (v.N <= 8) unit_dp1<V1, 8, false>(v, w, u, lds_raw, Yl, r, bt, &res1);
-            else if (v.N <= 16) unit_dp1<V1, 16, false>(v, w, u, lds_raw, Yl, r, bt, &res1);
-            else unit_dp1<V1, kMaxN, false>(v, w, u, lds_raw, Yl, r, bt, &res1);
-        }
+        if (v.span) unit_dp1<V1, NB, true, 1, false>(v, w, u, lds_raw, Yl, r, bt, none, nullptr, nullptr, nullptr, res, &res_c);
+        else unit_dp1<V1, NB, false, 1, false>(v, w, u, lds_raw, Yl, r, bt, none, nullptr, nullptr, nullptr, res, &res_c);
+        __syncthreads();
         if (threadIdx.x != 0) return;
-        w.uT[u] = res1;                                 // the unit's own minimum (kInf if pruned)
-        if (res1 != kInf) atomicMin(w.hdr, (unsigned long long)res1);
+        w.uT[p] = res[0];                               // the unit's own minimum (kInf if pruned)
+        if (res[0] != kInf) {
+            atomicMin(w.hdr, (unsigned long long)res[0]);
+            atomicMin(reinterpret_cast<unsigned long long *>(w.wT + u / v.nY), (unsigned long long)res[0]);
+        }
         return;
     }
-    const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, v.Rm, v.Km, STEP, false, v.span);
-    if (v.span) unit_dp<STEP, false, true>(v, w, u, L, Yl, r, bt, bq);
-    else unit_dp<STEP, false, false>(v, w, u, L, Yl, r, bt, bq);
-    if (threadIdx.x != 0) return;
+    Pack pk{};
     long long ct = kInf, cq = kInf;
     int bc = 0;
-    for (int c = 1; c <= v.Cm; c++) {
-        const size_t f = ((size_t)c * (v.W + 1) + v.W) * (v.N + 1) + v.N;
-        const long long t = L.FT[f], q = STEP == 2 ? L.FQ[f] : 0;
-        if (t != kInf && better<STEP>(q, t, cq, ct)) { ct = t; cq = q; bc = c; }
+    if (pack_for(v, w, pk)) {
+        using U = unsigned long long;
+        if (v.span) unit_dp1<U, NB, true, 2, false>(v, w, u, lds_raw, Yl, r, bq, pk, nullptr, nullptr, nullptr, res, &res_c);
+        else unit_dp1<U, NB, false, 2, false>(v, w, u, lds_raw, Yl, r, bq, pk, nullptr, nullptr, nullptr, res, &res_c);
+        __syncthreads();
+        if (threadIdx.x != 0) return;
+        cq = res[0];
+        ct = res[1];
+        bc = res_c;
+    } else {
+        const UnitLds L = unit_lds(lds_raw, v.W, v.N, v.Cm, v.Rm, v.Km, STEP, false, v.span);
+        if (v.span) unit_dp<STEP, false, true>(v, w, u, L, Yl, r, bt, bq);
+        else unit_dp<STEP, false, false>(v, w, u, L, Yl, r, bt, bq);
+        if (threadIdx.x != 0) return;
+        for (int c = 1; c <= v.Cm; c++) {
+            const size_t f = ((size_t)c * (v.W + 1) + v.W) * (v.N + 1) + v.N;
+            const long long t = L.FT[f], q = STEP == 2 ? L.FQ[f] : 0;
+            if (t != kInf && better<STEP>(q, t, cq, ct)) { ct = t; cq = q; bc = c; }
+        }
     }
-    w.uQ[u] = cq;
-    w.uT[u] = ct;
-    w.uC[u] = bc;
+    w.uQ[p] = cq;
+    w.uT[p] = ct;
+    w.uC[p] = bc;
     if (ct != kInf) atomicMin(w.hdr + 3, (unsigned long long)cq);
 }
 
-// Lexicographic minimum of (Q, T~, unit) over the units.
+// Lexicographic minimum of (Q, T~, unit) over the kept units (their list is in unit order, so
+// the least position is the first unit).
 __global__ void __launch_bounds__(1024)
 k_lit_pick(LitView v, LitWs w)
 {
@@ -701,15 +858,18 @@ k_lit_pick(LitView v, LitWs w)
 }
 
 // ---------------------------------------------------------------------------------------
-// Rebuild the winner and write the result (one wave; lane 0 walks the argmins back).
+// Rebuild the winner and write the result (four waves share the unit's DP; lane 0 walks the
+// argmins back).
 __host__ __device__ inline size_t final_lds_bytes(int W, int H, int N, int Cm, int Rm, int Km, int span)
 {
     const size_t knap = (size_t)(Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
-    return unit_lds_bytes(W, N, Cm, Rm, Km, 2, true, span) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile +
+    return rec_lds_bytes(W, N, Cm, Rm, Km, span) + ((17 * knap + 15) & ~size_t(15)) + 20 * tile +
            (size_t)Rm * Cm + 16 + 24 * (size_t)(H + 1) * (H + 1) + 16;
 }
 
-__global__ void __launch_bounds__(64)
+constexpr int kFinalThreads = 256;
+
+__global__ void __launch_bounds__(kFinalThreads)
 k_lit_final(LitView v, LitWs w, trs_result *out)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -723,7 +883,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
         for (size_t e = lane; e < sizeof(trs_result) / 4; e += blockDim.x) z[e] = 0;
     }
     const UnitLds L = unit_lds(lds_raw, W, N, v.Cm, v.Rm, Km, 2, true, v.span);
-    unsigned char *extra = lds_raw + unit_lds_bytes(W, N, v.Cm, v.Rm, Km, 2, true, v.span);
+    unsigned char *extra = lds_raw + rec_lds_bytes(W, N, v.Cm, v.Rm, Km, v.span);
     const size_t knap = (size_t)(v.Rm + 1) * (N + 1), tile = (size_t)(Km + 1) * (H + 1);
     long long *kT = reinterpret_cast<long long *>(extra), *kQ = kT + knap;
     unsigned char *kC = reinterpret_cast<unsigned char *>(kQ + knap);
@@ -735,10 +895,37 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
     const unsigned long long tmin = w.hdr[0];
     const bool feasible = tmin != kNone && w.hdr[1] != kNone;
     int r = 0;
+    // argmins of the column DP: the packed DP's when the keys fit, else the serial DP's
+    const unsigned char *AX = L.AX, *AK = L.AK;
     if (feasible) {
-        if (v.span) unit_dp<2, true, true>(v, w, (int)w.hdr[1], L, Yl, r, kInf, kInf);
-        else unit_dp<2, true, false>(v, w, (int)w.hdr[1], L, Yl, r, kInf, kInf);
+        Pack pk{};
+        if (pack_for(v, w, pk)) {
+            const size_t F = (size_t)(v.Cm + 1) * (W + 1) * (N + 1);
+            unsigned char *ax = lds_raw + ((unit1_lds_bytes(W, N, v.Cm, v.Rm, Km, 8, v.span) + 15) & ~size_t(15));
+            unsigned char *ak = ax + F;
+            unsigned *axk = reinterpret_cast<unsigned *>(ax + ((2 * F + 15) & ~size_t(15)));
+            __shared__ long long res2[2];
+            __shared__ int res2_c;
+            using U = unsigned long long;
+            const int u = v.ulist[(int)w.hdr[1]];
+            if (v.span) {
+                if (N <= 8) unit_dp1<U, 8, true, 2, true>(v, w, u, lds_raw, Yl, r, kInf, pk, ax, ak, axk, res2, &res2_c);
+                else if (N <= 16) unit_dp1<U, 16, true, 2, true>(v, w, u, lds_raw, Yl, r, kInf, pk, ax, ak, axk, res2, &res2_c);
+                else unit_dp1<U, kMaxN, true, 2, true>(v, w, u, lds_raw, Yl, r, kInf, pk, ax, ak, axk, res2, &res2_c);
+            } else {
+                if (N <= 8) unit_dp1<U, 8, false, 2, true>(v, w, u, lds_raw, Yl, r, kInf, pk, ax, ak, axk, res2, &res2_c);
+                else if (N <= 16) unit_dp1<U, 16, false, 2, true>(v, w, u, lds_raw, Yl, r, kInf, pk, ax, ak, axk, res2, &res2_c);
+                else unit_dp1<U, kMaxN, false, 2, true>(v, w, u, lds_raw, Yl, r, kInf, pk, ax, ak, axk, res2, &res2_c);
+            }
+            AX = ax;
+            AK = ak;
+        } else if (v.span) {
+            unit_dp<2, true, true>(v, w, v.ulist[(int)w.hdr[1]], L, Yl, r, kInf, kInf);
+        } else {
+            unit_dp<2, true, false>(v, w, v.ulist[(int)w.hdr[1]], L, Yl, r, kInf, kInf);
+        }
     }
+    __syncthreads();
     if (lane == 0) {
         auto rect_at = [&](const long long *a, int x0, int x1, int y0, int y1) {
             return a[(size_t)sidx(x0, x1, W) * v.R2 + ridx(y0, y1, H)];
@@ -791,7 +978,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
             }
         } else {
             const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
-            const int wi = (int)(w.hdr[1] / (unsigned long long)v.nY), c = (int)w.hdr[2];
+            const int wi = v.ulist[(int)w.hdr[1]] / v.nY, c = (int)w.hdr[2];
             const long long lo = v.win[wi];
             const long long hi = v.karea ? (long long)v.karea * lo : kInf;
             auto ok = [&](int x0, int x1, int y0, int y1) {
@@ -803,8 +990,8 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
             cx[c] = W;
             for (int i = c; i > 0; i--) {
                 const size_t f = ((size_t)i * (W + 1) + x) * (N + 1) + n;
-                cx[i - 1] = L.AX[f];
-                ck[i - 1] = L.AK[f];
+                cx[i - 1] = AX[f];
+                ck[i - 1] = AK[f];
                 x = cx[i - 1];
                 n -= ck[i - 1];
             }
@@ -869,7 +1056,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
     // emits the slices (a block of tiles is emitted at its top tile).
     if (feasible) {
         const int c = (int)w.hdr[2];
-        const int wi = (int)(w.hdr[1] / (unsigned long long)v.nY);
+        const int wi = v.ulist[(int)w.hdr[1]] / v.nY;
         const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
         const long long lo = v.win[wi];
         const long long hi = v.karea ? (long long)v.karea * lo : kInf;
@@ -974,15 +1161,15 @@ struct LitPlan {
     long long n_win = 0, nY = 0, n_units = 0, n_enumerated = 0;
     std::vector<int> colpx, rowpx;
     std::vector<long long> win;
-    std::vector<int> worder;
+    std::vector<int> ulist, dorder, wlive;
     std::vector<unsigned char> ytab, strip_xy, row_yy;
     std::vector<char> blob;             // the tables above, packed for the device copy
-    size_t o_col = 0, o_row = 0, o_win = 0, o_y = 0, o_sx = 0, o_ry = 0, o_wo = 0;
+    size_t o_col = 0, o_row = 0, o_win = 0, o_y = 0, o_sx = 0, o_ry = 0, o_ul = 0, o_do = 0, o_wl = 0;
     std::map<int, void *> dev;          // device copies of the tables
 };
 
 struct WsLayout {
-    size_t hdr, sat, rA, rT, rQ, tT, tQ, uQ, uT, uC, bytes;
+    size_t hdr, sat, rA, rT, rQ, tT, tQ, uQ, uT, uC, wT, bytes;
 };
 
 std::mutex g_mu;
@@ -992,7 +1179,11 @@ std::map<std::vector<long long>, LitPlan> g_plans;
 constexpr int kStages = 7;     // prefix sums + rectangles, tiles 1, units 1, tiles 2, units 2, pick, final
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-std::vector<std::array<hipEvent_t, kStages + 1>> g_prof_ev;
+struct ProfRun {
+    std::array<hipEvent_t, kStages + 1> ev;
+    unsigned long long *work;           // device: relaxations run in step 1 and step 2
+};
+std::vector<ProfRun> g_prof_ev;
 
 trs_status check_args(const trs_frame *f, const trs_search_params *p)
 {
@@ -1094,7 +1285,7 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
             pl.row_yy[2 * q] = (unsigned char)y0;
             pl.row_yy[2 * q + 1] = (unsigned char)y1;
         }
-    if (unit_lds_bytes(pl.W, pl.N, pl.Cm, pl.Rm, pl.Km, 2, false, pl.span) > kLdsLimit - 1024 ||
+    if (unit2_lds_bytes(pl.W, pl.N, pl.Cm, pl.Rm, pl.Km, pl.span) > kLdsLimit - 1024 ||
         final_lds_bytes(pl.W, pl.H, pl.N, pl.Cm, pl.Rm, pl.Km, pl.span) > kLdsLimit - 4 * 1024 ||
         (size_t)7 * 8 * pl.R2 > kLdsLimit)
         return TRS_ENOTIMPL;
@@ -1114,16 +1305,6 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
         for (long long a : areas)
             if (N * a <= At && (long long)pl.karea * N * a > At) pl.win.push_back(a);
     pl.n_win = (long long)pl.win.size();
-    // Dispatch order of the windows (speed only: ties are broken by unit index): nearest first
-    // to 3/4 of the mean RS area, where the smallest area of a balanced partition tends to lie,
-    // so that the pruning bounds tighten early.
-    pl.worder.resize(pl.win.size());
-    for (size_t i = 0; i < pl.win.size(); i++) pl.worder[i] = (int)i;
-    {
-        const double target = 0.75 * (double)At / (double)N;
-        auto dist = [&](int i) { return std::fabs(std::log(std::max<double>((double)pl.win[i], 1.0) / target)); };
-        std::stable_sort(pl.worder.begin(), pl.worder.end(), [&](int a, int b) { return dist(a) < dist(b); });
-    }
     // row boundaries: r = 1 .. Rm, each Y increasing from 0 to H, lexicographic
     pl.yrow = pl.Rm + 2;
     pl.ytab.clear();
@@ -1145,8 +1326,56 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
         }
     }
     pl.nY = (long long)pl.ytab.size() / pl.yrow;
-    pl.n_units = pl.n_win * pl.nY;
-    if (pl.n_units > kUnitCap) return TRS_ENOSPACE;
+    if (pl.n_win * pl.nY > kUnitCap) return TRS_ENOSPACE;
+    // Units kept: without blocks of tiles the RS of tile row j partition that full-width band of
+    // area A_j, so they number at least max(1, ceil(A_j / (k a - 1))) and at most
+    // min(Cm min(Km, h_j), floor(A_j / a)); a unit whose bands' ranges cannot hold N RS has no
+    // candidate and is dropped here (this part of the test depends on the geometry alone; the
+    // kernel adds the time bound).  With blocks every unit is kept.
+    pl.ulist.clear();
+    std::vector<long long> wstart(pl.n_win + 1, 0);
+    for (long long wi = 0; wi < pl.n_win; wi++) {
+        wstart[wi] = (long long)pl.ulist.size();
+        const long long a = pl.win[wi], k = pl.karea;
+        for (long long yi = 0; yi < pl.nY; yi++) {
+            bool keep = true;
+            if (!pl.span) {
+                const unsigned char *yt = &pl.ytab[(size_t)yi * pl.yrow];
+                long long lo = 0, hi = 0;
+                for (int j = 0; j < yt[0]; j++) {
+                    const int y0 = yt[1 + j], y1 = yt[2 + j];
+                    const long long A = (long long)pl.colpx[pl.W] * (pl.rowpx[y1] - pl.rowpx[y0]);
+                    long long mn = 1, mx = (long long)pl.Cm * std::min(pl.Km, y1 - y0);
+                    if (k > 0) {
+                        mn = std::max(mn, (A + k * a - 2) / (k * a - 1));
+                        mx = std::min(mx, A / a);
+                    }
+                    lo += mn;
+                    hi += mx < mn ? -(1ll << 40) : mx;
+                }
+                keep = lo <= N && hi >= N;
+            }
+            if (keep) pl.ulist.push_back((int)(wi * pl.nY + yi));
+        }
+    }
+    wstart[pl.n_win] = (long long)pl.ulist.size();
+    pl.n_units = (long long)pl.ulist.size();
+    pl.wlive.clear();
+    for (long long wi = 0; wi < pl.n_win; wi++)
+        if (wstart[wi + 1] > wstart[wi]) pl.wlive.push_back((int)wi);
+    // Dispatch order (speed only: ties are broken by unit order): windows nearest first to 3/4 of
+    // the mean RS area, where the smallest area of a balanced partition tends to lie, so that the
+    // pruning bounds tighten early; inside a window, unit order.
+    {
+        std::vector<int> wo(pl.n_win);
+        for (long long i = 0; i < pl.n_win; i++) wo[i] = (int)i;
+        const double target = 0.75 * (double)At / (double)N;
+        auto dist = [&](int i) { return std::fabs(std::log(std::max<double>((double)pl.win[i], 1.0) / target)); };
+        std::stable_sort(wo.begin(), wo.end(), [&](int x, int y) { return dist(x) < dist(y); });
+        pl.dorder.clear();
+        for (int wi : wo)
+            for (long long q = wstart[wi]; q < wstart[wi + 1]; q++) pl.dorder.push_back((int)q);
+    }
     if (pl.span) {
         pl.n_enumerated = span_count(pl, p->max_tile_cols);
         return TRS_OK;
@@ -1158,6 +1387,15 @@ trs_status build(const trs_frame *f, const trs_search_params *p, LitPlan &pl)
     if (st != TRS_OK) return st;
     pl.n_enumerated = n;
     return TRS_OK;
+}
+
+template <int STEP, class V1>
+void launch_units(int N, dim3 grid, size_t lds, hipStream_t stream, const LitView &v, const LitWs &w)
+{
+    const dim3 block(STEP == 1 ? 64 : 256);
+    if (N <= 8) hipLaunchKernelGGL((k_lit_units<STEP, V1, 8>), grid, block, lds, stream, v, w);
+    else if (N <= 16) hipLaunchKernelGGL((k_lit_units<STEP, V1, 16>), grid, block, lds, stream, v, w);
+    else hipLaunchKernelGGL((k_lit_units<STEP, V1, kMaxN>), grid, block, lds, stream, v, w);
 }
 
 WsLayout layout(const LitPlan &pl)
@@ -1173,9 +1411,10 @@ WsLayout layout(const LitPlan &pl)
     L.rQ = take(8 * nrect);
     L.tT = take(8 * ntab);
     L.tQ = take(8 * ntab);
-    L.uQ = take(8 * (size_t)pl.n_units);
-    L.uT = take(8 * (size_t)pl.n_units);
-    L.uC = take(4 * (size_t)pl.n_units);
+    L.uQ = take(8 * (size_t)std::max<long long>(pl.n_units, 1));
+    L.uT = take(8 * (size_t)std::max<long long>(pl.n_units, 1));
+    L.uC = take(4 * (size_t)std::max<long long>(pl.n_units, 1));
+    L.wT = take(8 * (size_t)std::max<long long>(pl.n_win, 1));
     L.bytes = off;
     return L;
 }
@@ -1221,7 +1460,9 @@ trs_status view_of(LitPlan &pl, const trs_search_params *p, LitView *v)
         pl.o_y = put(pl.blob, pl.ytab);
         pl.o_sx = put(pl.blob, pl.strip_xy);
         pl.o_ry = put(pl.blob, pl.row_yy);
-        pl.o_wo = put(pl.blob, pl.worder);
+        pl.o_ul = put(pl.blob, pl.ulist);
+        pl.o_do = put(pl.blob, pl.dorder);
+        pl.o_wl = put(pl.blob, pl.wlive);
     }
     auto it = pl.dev.find(dev);
     if (it == pl.dev.end()) {
@@ -1237,17 +1478,27 @@ trs_status view_of(LitPlan &pl, const trs_search_params *p, LitView *v)
     *v = LitView{};
     v->W = pl.W; v->H = pl.H; v->N = pl.N; v->Cm = pl.Cm; v->Rm = pl.Rm; v->Km = pl.Km;
     v->S = pl.S; v->R2 = pl.R2; v->n_win = (int)pl.n_win; v->nY = (int)pl.nY;
-    v->n_units = (int)pl.n_units; v->karea = pl.karea; v->yrow = pl.yrow; v->span = pl.span;
+    v->n_units = (int)pl.n_units; v->n_wlive = (int)pl.wlive.size(); v->karea = pl.karea; v->yrow = pl.yrow; v->span = pl.span;
     v->lam_num = p->lambda_num < 0 ? -1 : p->lambda_num;
     v->lam_den = p->lambda_den;
     v->n_enumerated = pl.n_enumerated;
+    // loop bounds of one unit: the strip DP relaxes min(Km, K) pairs per (x' < x, tile row, K),
+    // the column DP n pairs per (i <= min(x, Cm), x' in [i - 1, x), n)
+    long long knap = 0, colB = 0;
+    for (int K = 0; K <= pl.N; K++) knap += std::min(pl.Km, K);
+    for (int x = 1; x <= pl.W; x++)
+        for (int i = 1; i <= std::min(x, pl.Cm); i++) colB += (long long)(x - i + 1) * pl.N * (pl.N + 1) / 2;
+    v->relaxA = knap * pl.W * (pl.W + 1) / 2;
+    v->relaxB = colB;
     v->colpx = reinterpret_cast<const int *>(d + pl.o_col);
     v->rowpx = reinterpret_cast<const int *>(d + pl.o_row);
     v->win = reinterpret_cast<const long long *>(d + pl.o_win);
     v->ytab = reinterpret_cast<const unsigned char *>(d + pl.o_y);
     v->strip_xy = reinterpret_cast<const unsigned char *>(d + pl.o_sx);
     v->row_yy = reinterpret_cast<const unsigned char *>(d + pl.o_ry);
-    v->worder = reinterpret_cast<const int *>(d + pl.o_wo);
+    v->ulist = reinterpret_cast<const int *>(d + pl.o_ul);
+    v->dorder = reinterpret_cast<const int *>(d + pl.o_do);
+    v->wlive = reinterpret_cast<const int *>(d + pl.o_wl);
     return TRS_OK;
 }
 
@@ -1319,15 +1570,20 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
     w.uQ = reinterpret_cast<long long *>(ws + L.uQ);
     w.uT = reinterpret_cast<long long *>(ws + L.uT);
     w.uC = reinterpret_cast<int *>(ws + L.uC);
+    w.wT = reinterpret_cast<long long *>(ws + L.wT);
     std::array<hipEvent_t, kStages + 1> ev{};
     bool prof = false;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         prof = g_prof_on;
     }
-    if (prof)
+    unsigned long long *work = nullptr;
+    if (prof) {
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) return TRS_EDEVICE;
+        if (hipMalloc(&work, 2 * sizeof(unsigned long long)) != hipSuccess) return TRS_EDEVICE;
+        v.work = work;                  // cleared by k_lit_sat
+    }
     auto mark = [&](int i) { if (prof) (void)hipEventRecord(ev[i], stream); };
     const int nrect = v.S * v.R2;
     mark(0);
@@ -1336,48 +1592,53 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
     mark(1);
     if (v.n_units > 0) {
         const size_t tl = (size_t)7 * 8 * v.R2;
-        const dim3 gt((unsigned)(v.n_win * v.S)), gu((unsigned)v.n_units);
+        const dim3 gt((unsigned)(v.n_wlive * v.S)), gu((unsigned)v.n_units);
         hipLaunchKernelGGL(k_lit_tiles<1>, gt, dim3(256), tl, stream, v, w);
         mark(2);
-        hipLaunchKernelGGL((k_lit_units<1, unsigned>), gu, dim3(64),
-                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 4, v.span), stream, v, w);
-        hipLaunchKernelGGL((k_lit_units<1, unsigned long long>), gu, dim3(64),
-                           unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 8, v.span), stream, v, w);
+        launch_units<1, unsigned>(v.N, gu, unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 4, v.span), stream, v, w);
+        launch_units<1, unsigned long long>(v.N, gu, unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 8, v.span), stream, v, w);
         mark(3);
         hipLaunchKernelGGL(k_lit_tiles<2>, gt, dim3(256), tl, stream, v, w);
         mark(4);
-        hipLaunchKernelGGL(k_lit_units<2>, gu, dim3(64), unit_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 2, false, v.span), stream, v, w);
+        launch_units<2, unsigned long long>(v.N, gu, unit2_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, v.span), stream, v, w);
         mark(5);
         hipLaunchKernelGGL(k_lit_pick, dim3(1), dim3(1024), 0, stream, v, w);
         mark(6);
     } else {
         for (int i = 2; i <= 6; i++) mark(i);
     }
-    hipLaunchKernelGGL(k_lit_final, dim3(1), dim3(64), final_lds_bytes(v.W, v.H, v.N, v.Cm, v.Rm, v.Km, v.span),
+    hipLaunchKernelGGL(k_lit_final, dim3(1), dim3(kFinalThreads), final_lds_bytes(v.W, v.H, v.N, v.Cm, v.Rm, v.Km, v.span),
                        stream, v, w, out_dev);
     mark(7);
     if (prof) {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        g_prof_ev.push_back(ev);
+        g_prof_ev.push_back(ProfRun{ev, work});
     }
     return hipGetLastError() == hipSuccess ? TRS_OK : TRS_EDEVICE;
 }
 
-extern "C" trs_status trs_profile_read_literal(double *ms, int64_t *runs)
+extern "C" trs_status trs_profile_read_literal(double *ms, int64_t *runs, int64_t *relax)
 {
     using namespace trs::lit;
-    if (!ms || !runs) return TRS_EINVAL;
+    if (!ms || !runs || !relax) return TRS_EINVAL;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (int i = 0; i < kStages; i++) ms[i] = 0;
+    relax[0] = relax[1] = 0;
     trs_status st = TRS_OK;
-    for (auto &ev : g_prof_ev) {
+    for (auto &run : g_prof_ev) {
+        auto &ev = run.ev;
         if (hipEventSynchronize(ev[kStages]) != hipSuccess) st = TRS_EDEVICE;
         for (int i = 0; i < kStages && st == TRS_OK; i++) {
             float t = 0;
             if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = TRS_EDEVICE;
             ms[i] += t;
         }
+        unsigned long long n[2] = {0, 0};
+        if (st == TRS_OK && hipMemcpy(n, run.work, sizeof(n), hipMemcpyDeviceToHost) != hipSuccess) st = TRS_EDEVICE;
+        relax[0] += (int64_t)n[0];
+        relax[1] += (int64_t)n[1];
         for (auto &e : ev) (void)hipEventDestroy(e);
+        (void)hipFree(run.work);
     }
     *runs = (int64_t)g_prof_ev.size();
     g_prof_ev.clear();

@@ -92,6 +92,23 @@ def test_literal_search_with_totals_beyond_32_bits_matches_oracle(orc, w, h, N, 
     assert_same_result(got, ref, f"{w}x{h} N {N} wide totals")
 
 
+@pytest.mark.parametrize("w,h,N,C,R,K,lam", [(640, 512, 3, 3, 3, 2, (1, 10)), (1280, 768, 8, 4, 3, 4, (3, 10))])
+def test_literal_search_with_statistics_giving_negative_q_matches_oracle(orc, w, h, N, C, R, K, lam):
+    """S2 below S1^2 / n (no real pixels have such statistics) makes q negative, so step 2 and
+    the rebuild cannot pack (Q, T~) into one key and take the serial DP; the oracle keeps signed
+    Q and the results must still be equal.  Real statistics with small totals take the packed
+    DP (every other case here); totals past 2^32 take the serial one as well (the frame's S2
+    shifted by the bits of the Eq. 4 bound no longer fits below 2^61)."""
+    import numpy as np
+    luma, f, cost = _inputs(orc, w, h, 12)
+    s2 = (np.asarray(f["s2"], np.uint64) // np.uint64(3)).astype(np.uint64)
+    p = B.make_params(N, C, R, K, lam=lam, dtile=-1, drs=-1)
+    ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], s2)
+    assert ref["q_sel"] < 0
+    got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], s2)
+    assert_same_result(got, ref, f"{w}x{h} N {N} negative q")
+
+
 def test_literal_search_ctu64_matches_oracle(orc):
     """CTU 64 (a 30 x 17 grid on 1080p, finer areas: more windows)."""
     w, h, cs = 1920, 1080, 64
