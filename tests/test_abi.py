@@ -222,3 +222,13 @@ def test_literal_search_rejects_what_it_does_not_cover(lib):
     with pytest.raises(B.TrsError) as e:
         B.trs_literal_workspace(B.make_frame(7680, 4320), B.make_params(16, 8, 6, 4, dtile=-1, drs=-1))
     assert e.value.status == B.TRS_ENOTIMPL
+
+
+def test_literal_profile_read_without_searches(lib):
+    """With no literal search profiled the read returns zero stages, zero runs and zero
+    relaxations; a missing output pointer is rejected."""
+    st, runs, relax = B.trs_profile_read_literal()
+    assert runs == 0 and relax == (0, 0) and all(v == 0 for v in st.values())
+    ms = (ctypes.c_double * len(B.LITERAL_STAGES))()
+    n = ctypes.c_int64()
+    assert lib.trs_profile_read_literal(ms, ctypes.byref(n), None) == B.TRS_EINVAL

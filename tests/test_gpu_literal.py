@@ -184,3 +184,26 @@ def test_literal_search_with_spanning_blocks_matches_oracle(orc, w, h, N, C, R, 
     ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], f["s2"])
     got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], f["s2"])
     assert_same_result(got, ref, f"{w}x{h} N {N} spanning")
+
+
+def test_literal_profile_counts_the_relaxations_of_the_units_run(orc):
+    """While profiling, the search counts the DP relaxations of the units each step runs: step 2
+    runs a subset of the units step 1 ran (those within the Eq. 4 bound), and neither count can
+    exceed the count over every unit from the loop bounds."""
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    import bench
+    w, h, N, C, R, K = 1280, 768, 8, 4, 3, 4
+    luma, f, cost = _inputs(orc, w, h, 5)
+    p = B.make_params(N, C, R, K, lam=(1, 10), dtile=-1, drs=-1)
+    B.trs_profile_read_literal()                                  # forget earlier records
+    B.trs_profile_enable(True)
+    try:
+        got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], f["s2"])
+    finally:
+        B.trs_profile_enable(False)
+    st, runs, (r1, r2) = B.trs_profile_read_literal()
+    _, every = bench.literal_relaxations(w, h, N, C, R, K)
+    assert runs == 1 and got["status"] == 0
+    assert 0 < r2 <= r1 <= every
+    assert all(v >= 0 for v in st.values())
