@@ -1579,9 +1579,17 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
     }
     unsigned long long *work = nullptr;
     if (prof) {
-        for (auto &e : ev)
-            if (hipEventCreate(&e) != hipSuccess) return TRS_EDEVICE;
-        if (hipMalloc(&work, 2 * sizeof(unsigned long long)) != hipSuccess) return TRS_EDEVICE;
+        bool ok = true;
+        int made = 0;
+        for (auto &e : ev) {
+            if (hipEventCreate(&e) != hipSuccess) { ok = false; break; }
+            made++;
+        }
+        if (ok && hipMalloc(&work, 2 * sizeof(unsigned long long)) != hipSuccess) ok = false;
+        if (!ok) {                      // release what was made
+            for (int i = 0; i < made; i++) (void)hipEventDestroy(ev[i]);
+            return TRS_EDEVICE;
+        }
         v.work = work;                  // cleared by k_lit_sat
     }
     auto mark = [&](int i) { if (prof) (void)hipEventRecord(ev[i], stream); };
