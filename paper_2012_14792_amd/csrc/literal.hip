@@ -12,10 +12,12 @@
 //                 split of the tile's rows into k slices, one DP level per k (step 1: least
 //                 largest slice time, Eq. 1; step 2: least (Q, T~) with every slice time
 //                 within the Eq. 4 bound);
-//   k_lit_units   per (window, row boundaries Y): a DP over column boundaries whose state is
-//                 (tile columns used, RS used); the value of a column strip holding K RS comes
-//                 from a DP over its r tiles.  One wave per unit, a wavefront over the right
-//                 edge x of the strips, all state in LDS;
+//   k_lit_units   per (window, row boundaries Y) unit kept by the host (its tile-row bands can
+//                 hold N RS by area and slice count): a DP over column boundaries whose state
+//                 is (tile columns used, RS used); the value of a column strip holding K RS
+//                 comes from a DP over its r tiles.  One work-group per unit (one wave in step
+//                 1, four in step 2), a wavefront over the right edge x of the strips, all state
+//                 in LDS; step 2 on packed (Q, T~) keys when they fit 64 bits;
 //   k_lit_pick    the best unit: step 1 by an atomic minimum of T~min, step 2 by a reduction
 //                 over (Q, T~(P), unit);
 //   k_lit_final   one work-group redoes the winning unit keeping the argmins, rebuilds boundaries
