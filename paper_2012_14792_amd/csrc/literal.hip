@@ -979,14 +979,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
                 res.n_rs = n;
             }
         } else {
-            const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
-            const int wi = v.ulist[(int)w.hdr[1]] / v.nY, c = (int)w.hdr[2];
-            const long long lo = v.win[wi];
-            const long long hi = v.karea ? (long long)v.karea * lo : kInf;
-            auto ok = [&](int x0, int x1, int y0, int y1) {
-                const long long A = rect_at(w.rA, x0, x1, y0, y1);
-                return A >= lo && A < hi && (unsigned long long)rect_at(w.rT, x0, x1, y0, y1) <= tau;
-            };
+            const int c = (int)w.hdr[2];
             // column boundaries and RS count per strip, from the column DP's argmins
             int x = W, n = N;
             cx[c] = W;
@@ -1001,40 +994,67 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
             res.tile_rows = r;
             for (int i = 0; i <= c; i++) res.col_bd[i] = cx[i];
             for (int j = 0; j <= r; j++) res.row_bd[j] = Yl[j];
-            // every tile of a strip: its slice count k, or (blocks) kBlock + b on the top tile of a
-            // block of tiles ending at tile row b and 0 inside it; a DP over the tile-row levels,
-            // tiles first (k ascending) then blocks (a ascending), first minimum kept
-            constexpr int kBlock = 100;                   // above every slice count (k <= H <= 40)
-            for (int i = 0; i < c; i++) {
-                const size_t sb = (size_t)wi * v.S + sidx(cx[i], cx[i + 1], W);
-                for (int K = 0; K <= N; K++) { kT[K] = K == 0 ? 0 : kInf; kQ[K] = K == 0 ? 0 : kInf; }
-                for (int b = 1; b <= r; b++) {
-                    const size_t tb = (sb * v.R2 + ridx(Yl[b - 1], Yl[b], H)) * Km;
-                    for (int K = 0; K <= N; K++) {
-                        long long bt = kInf, bq = kInf;
-                        int bk = 0;
-                        for (int k = 1; k <= Km && k <= K; k++) {
-                            const long long at = kT[(b - 1) * (N + 1) + K - k], ct = w.tT[tb + k - 1];
-                            if (at == kInf || ct == kInf) continue;
-                            const long long t = at > ct ? at : ct;
-                            const long long q = kQ[(b - 1) * (N + 1) + K - k] + w.tQ[tb + k - 1];
-                            if (better<2>(q, t, bq, bt)) { bt = t; bq = q; bk = k; }
-                        }
-                        if (v.span && K >= 1)
-                            for (int a = 0; a + 2 <= b; a++) {
-                                if (!ok(cx[i], cx[i + 1], Yl[a], Yl[b])) continue;
-                                const long long at = kT[a * (N + 1) + K - 1];
-                                if (at == kInf) continue;
-                                const long long bT = rect_at(w.rT, cx[i], cx[i + 1], Yl[a], Yl[b]);
-                                const long long t = at > bT ? at : bT;
-                                const long long q = kQ[a * (N + 1) + K - 1] + rect_at(w.rQ, cx[i], cx[i + 1], Yl[a], Yl[b]);
-                                if (better<2>(q, t, bq, bt)) { bt = t; bq = q; bk = kBlock + a; }
-                            }
-                        kT[b * (N + 1) + K] = bt;
-                        kQ[b * (N + 1) + K] = bq;
-                        kC[b * (N + 1) + K] = (unsigned char)bk;
+        }
+    }
+    __syncthreads();
+    // Tiles in raster order, slices top to bottom.  For a tile cut into slices, all lanes copy
+    // its rectangles' area, time and q into LDS, then lane 0 redoes the tile DP from there and
+    // emits the slices (a block of tiles is emitted at its top tile).
+    if (feasible) {
+        const int c = (int)w.hdr[2];
+        const int wi = v.ulist[(int)w.hdr[1]] / v.nY;
+        const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
+        const long long lo = v.win[wi];
+        const long long hi = v.karea ? (long long)v.karea * lo : kInf;
+        constexpr int kBlock = 100;                       // above every slice count (k <= H <= 40)
+        auto rect_at = [&](const long long *a, int x0, int x1, int y0, int y1) {
+            return a[(size_t)sidx(x0, x1, W) * v.R2 + ridx(y0, y1, H)];
+        };
+        auto ok = [&](int x0, int x1, int y0, int y1) {
+            const long long A = rect_at(w.rA, x0, x1, y0, y1);
+            return A >= lo && A < hi && (unsigned long long)rect_at(w.rT, x0, x1, y0, y1) <= tau;
+        };
+        // Every tile of a strip: its slice count k, or (blocks) kBlock + b on the top tile of a
+        // block of tiles ending at tile row b and 0 inside it.  A DP over the tile-row levels,
+        // strip by strip, the lanes taking the RS counts K of a level; per (level, K) tiles are
+        // tried first (k ascending), then blocks (a ascending), first minimum kept.  Lane 0 walks
+        // the choices back.
+        for (int i = 0; i < c; i++) {
+            const size_t sb = (size_t)wi * v.S + sidx(cx[i], cx[i + 1], W);
+            for (int K = lane; K <= N; K += blockDim.x) {
+                kT[K] = K == 0 ? 0 : kInf;
+                kQ[K] = K == 0 ? 0 : kInf;
+            }
+            __syncthreads();
+            for (int b = 1; b <= r; b++) {
+                const size_t tb = (sb * v.R2 + ridx(Yl[b - 1], Yl[b], H)) * Km;
+                for (int K = lane; K <= N; K += blockDim.x) {
+                    long long bt = kInf, bq = kInf;
+                    int bk = 0;
+                    for (int k = 1; k <= Km && k <= K; k++) {
+                        const long long at = kT[(b - 1) * (N + 1) + K - k], ct = w.tT[tb + k - 1];
+                        if (at == kInf || ct == kInf) continue;
+                        const long long t = at > ct ? at : ct;
+                        const long long q = kQ[(b - 1) * (N + 1) + K - k] + w.tQ[tb + k - 1];
+                        if (better<2>(q, t, bq, bt)) { bt = t; bq = q; bk = k; }
                     }
+                    if (v.span && K >= 1)
+                        for (int a = 0; a + 2 <= b; a++) {
+                            if (!ok(cx[i], cx[i + 1], Yl[a], Yl[b])) continue;
+                            const long long at = kT[a * (N + 1) + K - 1];
+                            if (at == kInf) continue;
+                            const long long bT = rect_at(w.rT, cx[i], cx[i + 1], Yl[a], Yl[b]);
+                            const long long t = at > bT ? at : bT;
+                            const long long q = kQ[a * (N + 1) + K - 1] + rect_at(w.rQ, cx[i], cx[i + 1], Yl[a], Yl[b]);
+                            if (better<2>(q, t, bq, bt)) { bt = t; bq = q; bk = kBlock + a; }
+                        }
+                    kT[b * (N + 1) + K] = bt;
+                    kQ[b * (N + 1) + K] = bq;
+                    kC[b * (N + 1) + K] = (unsigned char)bk;
                 }
+                __syncthreads();
+            }
+            if (lane == 0) {
                 for (int j = 0; j < r; j++) tcnt[j * v.Cm + i] = 0;
                 for (int b = r, K = ck[i]; b > 0;) {
                     const int ch = kC[b * (N + 1) + K];
@@ -1050,19 +1070,8 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
                     }
                 }
             }
+            __syncthreads();                          // the next strip reuses the DP levels
         }
-    }
-    __syncthreads();
-    // Tiles in raster order, slices top to bottom.  For a tile cut into slices, all lanes copy
-    // its rectangles' area, time and q into LDS, then lane 0 redoes the tile DP from there and
-    // emits the slices (a block of tiles is emitted at its top tile).
-    if (feasible) {
-        const int c = (int)w.hdr[2];
-        const int wi = v.ulist[(int)w.hdr[1]] / v.nY;
-        const unsigned long long tau = eq4_bound(tmin, v.lam_num, v.lam_den);
-        const long long lo = v.win[wi];
-        const long long hi = v.karea ? (long long)v.karea * lo : kInf;
-        constexpr int kBlock = 100;
         long long *sA = reinterpret_cast<long long *>(                  // after tcnt
             (reinterpret_cast<uintptr_t>(tcnt + (size_t)v.Rm * v.Cm) + 15) & ~uintptr_t(15));
         const int HP = H + 1;
