@@ -998,7 +998,7 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
     }
     __syncthreads();
     // Tiles in raster order, slices top to bottom.  For a tile cut into slices, all lanes copy
-    // its rectangles' area, time and q into LDS, then lane 0 redoes the tile DP from there and
+    // its rectangles' area, time and q into LDS and redo the tile DP from there, then lane 0
     // emits the slices (a block of tiles is emitted at its top tile).
     if (feasible) {
         const int c = (int)w.hdr[2];
@@ -1109,30 +1109,39 @@ k_lit_final(LitView v, LitWs w, trs_result *out)
                     sT[(ya - y0) * HP + (yb - y0)] = w.rT[ri];
                     sQ[(ya - y0) * HP + (yb - y0)] = w.rQ[ri];
                 }
+                // the tile's split DP, the lanes taking the end rows y of a level (first
+                // minimum over the split rows yp in ascending order, as in the oracle)
+                auto ok = [&](int ya, int yb) {
+                    const long long A = sA[(ya - y0) * HP + (yb - y0)];
+                    return A >= lo && A < hi && (unsigned long long)sT[(ya - y0) * HP + (yb - y0)] <= tau;
+                };
+                auto at = [&](int q, int y) { return (size_t)q * (H + 1) + y; };
+                for (int e = lane; e < (kq + 1) * (hh + 1); e += blockDim.x) {
+                    const int q = e / (hh + 1), y = y0 + e % (hh + 1);
+                    const bool start = q == 0 && y == y0;
+                    fT[at(q, y)] = start ? 0 : kInf;
+                    fQ[at(q, y)] = start ? 0 : kInf;
+                    fA[at(q, y)] = -1;
+                }
                 __syncthreads();
+                for (int q = 1; q <= kq; q++) {
+                    for (int y = y0 + q + lane; y <= y1; y += blockDim.x) {
+                        long long bt = kInf, bq = kInf;
+                        int ba = -1;
+                        for (int yp = y0 + q - 1; yp < y; yp++) {
+                            if (fT[at(q - 1, yp)] == kInf || !ok(yp, y)) continue;
+                            const long long st = sT[(yp - y0) * HP + (y - y0)];
+                            const long long t = fT[at(q - 1, yp)] > st ? fT[at(q - 1, yp)] : st;
+                            const long long qq = fQ[at(q - 1, yp)] + sQ[(yp - y0) * HP + (y - y0)];
+                            if (better<2>(qq, t, bq, bt)) { bt = t; bq = qq; ba = yp; }
+                        }
+                        fT[at(q, y)] = bt;
+                        fQ[at(q, y)] = bq;
+                        fA[at(q, y)] = ba;
+                    }
+                    __syncthreads();
+                }
                 if (lane == 0) {
-                    auto ok = [&](int ya, int yb) {
-                        const long long A = sA[(ya - y0) * HP + (yb - y0)];
-                        return A >= lo && A < hi && (unsigned long long)sT[(ya - y0) * HP + (yb - y0)] <= tau;
-                    };
-                    auto at = [&](int q, int y) { return (size_t)q * (H + 1) + y; };
-                    for (int q = 0; q <= kq; q++)
-                        for (int y = y0; y <= y1; y++) { fT[at(q, y)] = kInf; fQ[at(q, y)] = kInf; fA[at(q, y)] = -1; }
-                    fT[at(0, y0)] = 0;
-                    fQ[at(0, y0)] = 0;
-                    for (int q = 1; q <= kq; q++)
-                        for (int y = y0 + q; y <= y1; y++)
-                            for (int yp = y0 + q - 1; yp < y; yp++) {
-                                if (fT[at(q - 1, yp)] == kInf || !ok(yp, y)) continue;
-                                const long long st = sT[(yp - y0) * HP + (y - y0)];
-                                const long long t = fT[at(q - 1, yp)] > st ? fT[at(q - 1, yp)] : st;
-                                const long long qq = fQ[at(q - 1, yp)] + sQ[(yp - y0) * HP + (y - y0)];
-                                if (better<2>(qq, t, fQ[at(q, y)], fT[at(q, y)])) {
-                                    fT[at(q, y)] = t;
-                                    fQ[at(q, y)] = qq;
-                                    fA[at(q, y)] = yp;
-                                }
-                            }
                     int rows[kMaxH + 1];
                     rows[kq] = y1;
                     for (int q = kq, y = y1; q > 0; q--) { y = fA[at(q, y)]; rows[q - 1] = y; }
