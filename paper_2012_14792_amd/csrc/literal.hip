@@ -186,8 +186,11 @@ k_lit_rects(LitView v, LitWs w)
 // ---------------------------------------------------------------------------------------
 // Tile tables: one work-group per (window, strip).  Threads take row pairs (y0, y); level q
 // holds the best split of rows [y0, y) into q slices.
-// BS threads: 128 in step 1, 256 in step 2 (measured best of 64, 128 and 256 for each).
-template <int STEP, int BS = STEP == 1 ? 128 : 256>
+// BS threads: 128 in step 1, 256 in step 2 (measured best of 64, 128 and 256 for each).  BUF:
+// every level of the DP is kept in LDS, [row pair][k] as in the table, and the table block is
+// written at the end in one coalesced pass (when 8 R2 (2 + Km) bytes, 8 R2 (3 + 2 Km) with Q,
+// fit); else two levels are kept and each level is written as it is computed.
+template <int STEP, bool BUF, int BS = STEP == 1 ? 128 : 256>
 __global__ void __launch_bounds__(BS)
 k_lit_tiles(LitView v, LitWs w)
 {
@@ -196,9 +199,9 @@ k_lit_tiles(LitView v, LitWs w)
     const int wi = v.wlive[blockIdx.x / v.S], s = blockIdx.x % v.S;
     long long *sA = reinterpret_cast<long long *>(lds_raw);
     long long *sT = sA + R2;
-    long long *sQ = sT + R2;
-    long long *fT = sQ + R2;            // two levels, R2 entries each
-    long long *fQ = fT + 2 * R2;
+    long long *sQ = sT + (STEP == 2 ? R2 : 0);
+    long long *fT = sQ + R2;            // BUF: R2 x Km levels; else two levels of R2 entries
+    long long *fQ = fT + (BUF ? (size_t)R2 * Km : 2 * (size_t)R2);
     unsigned long long tau = kNone;
     if (STEP == 2) {
         const unsigned long long tmin = w.hdr[0];
@@ -220,10 +223,12 @@ k_lit_tiles(LitView v, LitWs w)
     auto ok = [&](int p) {
         return sA[p] >= lo && sA[p] < hi && (STEP == 1 || (unsigned long long)sT[p] <= tau);
     };
+    // level q of pair p
+    auto cur = [&](long long *f, int p, int q) -> long long & {
+        return BUF ? f[(size_t)p * Km + (q - 1)] : f[(size_t)(q & 1) * R2 + p];
+    };
     const size_t tbase = ((size_t)wi * v.S + s) * R2;
     for (int q = 1; q <= Km; q++) {
-        long long *curT = fT + (q & 1) * R2, *prvT = fT + ((q - 1) & 1) * R2;
-        long long *curQ = fQ + (q & 1) * R2, *prvQ = fQ + ((q - 1) & 1) * R2;
         for (int p = threadIdx.x; p < R2; p += blockDim.x) {
             const int y0 = v.row_yy[2 * p], y = v.row_yy[2 * p + 1];
             long long bt = kInf, bq = kInf;
@@ -232,19 +237,27 @@ k_lit_tiles(LitView v, LitWs w)
             } else {
                 for (int yp = y0 + q - 1; yp < y; yp++) {
                     const int pp = ridx(y0, yp, H), ps = ridx(yp, y, H);
-                    if (prvT[pp] == kInf || !ok(ps)) continue;
-                    const long long t = prvT[pp] > sT[ps] ? prvT[pp] : sT[ps];
-                    const long long qq = STEP == 2 ? prvQ[pp] + sQ[ps] : 0;
+                    const long long pt = cur(fT, pp, q - 1);
+                    if (pt == kInf || !ok(ps)) continue;
+                    const long long t = pt > sT[ps] ? pt : sT[ps];
+                    const long long qq = STEP == 2 ? cur(fQ, pp, q - 1) + sQ[ps] : 0;
                     if (better<STEP>(qq, t, bq, bt)) { bt = t; bq = qq; }
                 }
             }
-            curT[p] = bt;
-            if (STEP == 2) curQ[p] = bq;
-            w.tT[(tbase + p) * Km + (q - 1)] = bt;
-            if (STEP == 2) w.tQ[(tbase + p) * Km + (q - 1)] = bq;
+            cur(fT, p, q) = bt;
+            if (STEP == 2) cur(fQ, p, q) = bq;
+            if (!BUF) {
+                w.tT[(tbase + p) * Km + (q - 1)] = bt;
+                if (STEP == 2) w.tQ[(tbase + p) * Km + (q - 1)] = bq;
+            }
         }
         __syncthreads();
     }
+    if (BUF)
+        for (size_t e = threadIdx.x; e < (size_t)R2 * Km; e += blockDim.x) {
+            w.tT[tbase * Km + e] = fT[e];
+            if (STEP == 2) w.tQ[tbase * Km + e] = fQ[e];
+        }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1620,14 +1633,17 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
     hipLaunchKernelGGL(k_lit_rects, dim3((nrect + 255) / 256), dim3(256), 0, stream, v, w);
     mark(1);
     if (v.n_units > 0) {
-        const size_t tl = (size_t)7 * 8 * v.R2;
+        const size_t tl = (size_t)7 * 8 * v.R2;                    // two levels kept
+        const size_t tb1 = (size_t)8 * v.R2 * (2 + v.Km), tb2 = (size_t)8 * v.R2 * (3 + 2 * v.Km);
         const dim3 gt((unsigned)(v.n_wlive * v.S)), gu((unsigned)v.n_units);
-        hipLaunchKernelGGL(k_lit_tiles<1>, gt, dim3(128), tl, stream, v, w);
+        if (tb1 <= kLdsLimit - 1024) hipLaunchKernelGGL((k_lit_tiles<1, true>), gt, dim3(128), tb1, stream, v, w);
+        else hipLaunchKernelGGL((k_lit_tiles<1, false>), gt, dim3(128), tl, stream, v, w);
         mark(2);
         launch_units<1, unsigned>(v.N, gu, unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 4, v.span), stream, v, w);
         launch_units<1, unsigned long long>(v.N, gu, unit1_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, 8, v.span), stream, v, w);
         mark(3);
-        hipLaunchKernelGGL(k_lit_tiles<2>, gt, dim3(256), tl, stream, v, w);
+        if (tb2 <= kLdsLimit - 1024) hipLaunchKernelGGL((k_lit_tiles<2, true>), gt, dim3(256), tb2, stream, v, w);
+        else hipLaunchKernelGGL((k_lit_tiles<2, false>), gt, dim3(256), tl, stream, v, w);
         mark(4);
         launch_units<2, unsigned long long>(v.N, gu, unit2_lds_bytes(v.W, v.N, v.Cm, v.Rm, v.Km, v.span), stream, v, w);
         mark(5);

@@ -115,6 +115,20 @@ def test_literal_search_with_statistics_giving_negative_q_matches_oracle(orc, w,
     assert_same_result(got, ref, f"{w}x{h} N {N} negative q")
 
 
+@pytest.mark.parametrize("N,C,R,K", [(6, 2, 2, 12), (8, 3, 2, 12)])
+def test_literal_search_tall_frame_with_many_slices_per_tile_matches_oracle(orc, N, C, R, K):
+    """A 1024x5120 frame (8 x 40 CTUs, 820 row pairs) with up to 12 slices per tile: the step-2
+    tile tables no longer fit LDS with every DP level (8 x 820 x 27 bytes), so that pass keeps two
+    levels and writes each as it goes, while step 1 keeps every level; the result equals the
+    oracle's."""
+    w, h = 1024, 5120
+    luma, f, cost = _inputs(orc, w, h, 4)
+    p = B.make_params(N, C, R, K, lam=(1, 10), dtile=-1, drs=-1)
+    ref = orc.literal_search(w, h, oracle_params(orc, p), cost, f["s1"], f["s2"])
+    got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], f["s2"])
+    assert_same_result(got, ref, f"{w}x{h} N {N} K {K}")
+
+
 def test_literal_search_ctu64_matches_oracle(orc):
     """CTU 64 (a 30 x 17 grid on 1080p, finer areas: more windows)."""
     w, h, cs = 1920, 1080, 64
