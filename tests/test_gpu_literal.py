@@ -221,3 +221,44 @@ def test_literal_profile_counts_the_relaxations_of_the_units_run(orc):
     assert runs == 1 and got["status"] == 0
     assert 0 < r2 <= r1 <= every
     assert all(v >= 0 for v in st.values())
+
+
+def _kept_units(w, h, N, Cm, Rm, Km, k, cs=128):
+    """Units (area window, row boundaries) whose tile-row bands can hold N RS: per band of area
+    A, at least max(1, ceil(A / (k a - 1))) and at most min(Cm min(Km, h), floor(A / a)) RS."""
+    from itertools import combinations
+    W, H = (w + cs - 1) // cs, (h + cs - 1) // cs
+    Cm, Rm, Km = min(Cm, W), min(Rm, H), min(Km, H)
+    colpx, rowpx = [0], [0]
+    for x in range(W):
+        colpx.append(colpx[-1] + min(cs, w - x * cs))
+    for y in range(H):
+        rowpx.append(rowpx[-1] + min(cs, h - y * cs))
+    areas = {(colpx[x1] - colpx[x0]) * (rowpx[y1] - rowpx[y0])
+             for x0 in range(W) for x1 in range(x0 + 1, W + 1) for y0 in range(H) for y1 in range(y0 + 1, H + 1)}
+    total = colpx[W] * rowpx[H]
+    wins = sorted(a for a in areas if N * a <= total < k * N * a)
+    kept = 0
+    for a in wins:
+        for r in range(1, Rm + 1):
+            for mid in combinations(range(1, H), r - 1):
+                Y = (0,) + mid + (H,)
+                lo = hi = 0
+                for y0, y1 in zip(Y, Y[1:]):
+                    A = colpx[W] * (rowpx[y1] - rowpx[y0])
+                    mn = max(1, -(-A // (k * a - 1)))
+                    mx = min(Cm * min(Km, y1 - y0), A // a)
+                    lo += mn
+                    hi += mx if mx >= mn else -(1 << 40)
+                kept += lo <= N <= hi
+    return kept
+
+
+@pytest.mark.parametrize("w,h,N,C,R,K", [(1280, 768, 8, 4, 3, 4), (1920, 1080, 8, 6, 4, 4)])
+def test_literal_search_counts_the_units_kept_by_the_band_test(orc, w, h, N, C, R, K):
+    """n_step2 reports the units searched: those whose bands can hold N RS by area and slice
+    count, counted here independently."""
+    luma, f, cost = _inputs(orc, w, h, 2)
+    p = B.make_params(N, C, R, K, lam=(1, 10), dtile=-1, drs=-1)
+    got = gpu_literal(B.make_frame(w, h), p, cost, f["s1"], f["s2"])
+    assert got["n_step2"] == _kept_units(w, h, N, C, R, K, 3)
