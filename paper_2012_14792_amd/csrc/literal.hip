@@ -117,48 +117,46 @@ __device__ __forceinline__ bool better(long long aq, long long at, long long bq,
 }
 
 // ---------------------------------------------------------------------------------------
-// Prefix sums of T~, S1, S2 (one work-group) and the header.
+// Prefix sums of T~, S1, S2 (one work-group, scanned in LDS: rows, then columns) and the
+// header.
 __global__ void __launch_bounds__(256)
 k_lit_sat(LitView v, LitWs w, const uint32_t *__restrict__ cost, const uint32_t *__restrict__ s1,
           const uint64_t *__restrict__ s2)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    long long *sh = reinterpret_cast<long long *>(lds_raw);      // [3][(H + 1) x (W + 1)]
     const int W = v.W, H = v.H, P = (W + 1) * (H + 1);
     if (threadIdx.x == 0) {
         w.hdr[0] = kNone;
         w.hdr[1] = kNone;
         w.hdr[2] = 0;
         w.hdr[3] = kNone;
-        w.hdr[4] = 0;
         w.hdr[5] = 0;
         if (v.work) { v.work[0] = 0; v.work[1] = 0; }
     }
     for (int i = threadIdx.x; i < v.n_win; i += blockDim.x) w.wT[i] = kInf;
-    // rows: running sums along x
-    for (int t = threadIdx.x; t < 3 * (H + 1); t += blockDim.x) {
-        const int a = t / (H + 1), y = t % (H + 1);
-        long long *row = w.sat + (size_t)a * P + (size_t)y * (W + 1);
-        long long acc = 0;
-        row[0] = 0;
-        for (int x = 1; x <= W; x++) {
-            if (y > 0) {
-                const size_t c = (size_t)(y - 1) * W + (x - 1);
-                acc += a == 0 ? (long long)cost[c] : a == 1 ? (long long)s1[c] : (long long)s2[c];
-            }
-            row[x] = acc;
+    for (int e = threadIdx.x; e < 3 * P; e += blockDim.x) {
+        const int a = e / P, rem = e - a * P, y = rem / (W + 1), x = rem - y * (W + 1);
+        long long val = 0;
+        if (x > 0 && y > 0) {
+            const size_t c = (size_t)(y - 1) * W + (x - 1);
+            val = a == 0 ? (long long)cost[c] : a == 1 ? (long long)s1[c] : (long long)s2[c];
         }
+        sh[e] = val;
     }
     __syncthreads();
-    // columns: running sums along y
-    for (int t = threadIdx.x; t < 3 * (W + 1); t += blockDim.x) {
-        const int a = t / (W + 1), x = t % (W + 1);
-        long long *base = w.sat + (size_t)a * P + x;
-        long long acc = 0;
-        for (int y = 0; y <= H; y++) {
-            acc += base[(size_t)y * (W + 1)];
-            base[(size_t)y * (W + 1)] = acc;
-        }
-        if (a == 0 && x == W) w.hdr[4] = acc < 0xffffffffll;   // every time sum fits 32 bits
+    for (int t = threadIdx.x; t < 3 * (H + 1); t += blockDim.x) {           // rows: along x
+        long long *row = sh + (size_t)(t / (H + 1)) * P + (size_t)(t % (H + 1)) * (W + 1);
+        for (int x = 1; x <= W; x++) row[x] += row[x - 1];
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 3 * (W + 1); t += blockDim.x) {           // columns: along y
+        long long *col = sh + (size_t)(t / (W + 1)) * P + (t % (W + 1));
+        for (int y = 1; y <= H; y++) col[(size_t)y * (W + 1)] += col[(size_t)(y - 1) * (W + 1)];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * P; e += blockDim.x) w.sat[e] = sh[e];
+    if (threadIdx.x == 0) w.hdr[4] = sh[P - 1] < 0xffffffffll;          // every time sum fits 32 bits
 }
 
 // Area, time and q = S2 - floor(S1^2 / n) of every rectangle.
@@ -1629,7 +1627,8 @@ extern "C" trs_status trs_literal_search(const trs_frame *frame, const trs_searc
     auto mark = [&](int i) { if (prof) (void)hipEventRecord(ev[i], stream); };
     const int nrect = v.S * v.R2;
     mark(0);
-    hipLaunchKernelGGL(k_lit_sat, dim3(1), dim3(256), 0, stream, v, w, cost, s1, s2);
+    hipLaunchKernelGGL(k_lit_sat, dim3(1), dim3(256), (size_t)3 * 8 * (v.W + 1) * (v.H + 1), stream, v, w,
+                       cost, s1, s2);
     hipLaunchKernelGGL(k_lit_rects, dim3((nrect + 255) / 256), dim3(256), 0, stream, v, w);
     mark(1);
     if (v.n_units > 0) {
