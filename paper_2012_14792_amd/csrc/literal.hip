@@ -842,10 +842,24 @@ k_lit_pick(LitView v, LitWs w)
     if (w.hdr[0] == kNone) return;
     long long bq = kInf, bt = kInf;
     int bu = INT_MAX;
-    for (int u = threadIdx.x; u < v.n_units; u += blockDim.x) {
-        const long long q = w.uQ[u], t = w.uT[u];
-        if (q == kInf) continue;
-        if (q < bq || (q == bq && (t < bt || (t == bt && u < bu)))) { bq = q; bt = t; bu = u; }
+    // eight units per thread in flight (the comparison includes the position, so the order in
+    // which a thread visits its units does not matter)
+    constexpr int kPer = 8;
+    for (int u0 = threadIdx.x; u0 < v.n_units; u0 += kPer * blockDim.x) {
+        long long qv[kPer], tv[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; j++) {
+            const int u = u0 + j * (int)blockDim.x;
+            qv[j] = u < v.n_units ? w.uQ[u] : kInf;
+            tv[j] = u < v.n_units ? w.uT[u] : kInf;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; j++) {
+            const int u = u0 + j * (int)blockDim.x;
+            const long long q = qv[j], t = tv[j];
+            if (q == kInf) continue;
+            if (q < bq || (q == bq && (t < bt || (t == bt && u < bu)))) { bq = q; bt = t; bu = u; }
+        }
     }
     sq[threadIdx.x] = bq;
     st[threadIdx.x] = bt;
